@@ -1,0 +1,235 @@
+/*
+ * gs.h - C ABI of the MI355X (gfx950) tile rasterizer for 3D Gaussian splats.
+ *
+ * The method is the differentiable tile rasterizer of Kerbl et al., "3D Gaussian
+ * Splatting for Real-Time Radiance Field Rendering" (SIGGRAPH 2023), Sec. 6 and
+ * App. C, Alg. 2: Rasterize(w, h, M, S, C, A, V) over means M, covariances S
+ * (stored as scales and rotation quaternions, Sec. 4), SH colours C (Sec. 5),
+ * opacities A and a view V; and its backward pass (Sec. 6 and App. A).
+ *
+ * One forward pass is
+ *     gs_project -> gs_bin -> gs_sort -> gs_render_fwd
+ * and the matching backward pass is
+ *     gs_render_bwd -> gs_project_bwd.
+ * Every stage accepts V >= 1 views at once: Gaussians are projected into all
+ * views, instances of all views are sorted together under a global tile id,
+ * and the render kernels process the tiles of all views in one launch.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Memory: every pointer inside the structs below is a DEVICE pointer owned by
+ *   the caller (e.g. a torch tensor). The structs themselves, the camera array
+ *   and the config are HOST memory, read during the call and not retained. The
+ *   library never allocates, frees or synchronises; scratch memory is passed in
+ *   as a caller-owned workspace whose size the *_workspace_bytes queries give.
+ * - Streams: every call only enqueues kernels on `stream` (0 = the null stream)
+ *   and returns; the sequence is capturable into a HIP graph.
+ * - Errors: the return value reports argument errors found on the host
+ *   (GS_ERR_ARG, GS_ERR_UNSUPPORTED) and launch failures (GS_ERR_HIP). Errors that
+ *   can only be known on the device (too many instances for the capacity, a sort
+ *   look-back that did not complete) are OR-ed into the device status word
+ *   gs_instances.status; read it after the stream completes (gs_read_status).
+ *   On a device-side error the outputs are unspecified but every kernel stays
+ *   inside the caller's buffers.
+ * - Culled or degenerate Gaussians (non-finite input, zero quaternion, depth
+ *   below near_z, non-positive-definite 2D covariance, empty pixel box) are not
+ *   errors: they get tiles_touched = 0 and zero gradients.
+ * - Parameter layout is structure-of-arrays (coalesced per plane):
+ *     means [3][N], log_scales [3][N], quats [4][N] as (r, i, j, k),
+ *     opacity_logits [N], sh [K][3][N] with K = (sh_degree + 1)^2.
+ * - Camera: world-to-camera rotation R (row-major) and translation t, pinhole
+ *   intrinsics in pixels, OpenCV axes (x right, y down, z forward); pixel (i, j)
+ *   has its centre at (i + 0.5, j + 0.5).
+ */
+#ifndef GS_MI355X_H
+#define GS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gs_stream_t; /* identical to hipStream_t */
+
+#define GS_MAX_VIEWS 32        /* views per call */
+#define GS_MAX_DIM 32767       /* largest image width or height */
+#define GS_RECORD_FLOATS 12    /* floats per projected Gaussian record */
+#define GS_GRAD2D_FLOATS 9     /* floats per screen-space gradient record */
+#define GS_MAX_INSTANCES ((int64_t)1 << 30) /* largest instance capacity */
+
+enum {
+  GS_OK = 0,
+  GS_ERR_ARG = -1,         /* null pointer, negative size, bad config value */
+  GS_ERR_CAPACITY = -2,    /* device status: more instances than capacity */
+  GS_ERR_HIP = -3,         /* a HIP launch failed */
+  GS_ERR_UNSUPPORTED = -4, /* size beyond a documented limit */
+  GS_ERR_SORT = -5         /* device status: sort look-back did not complete */
+};
+
+/* bits of the device status word */
+#define GS_STATUS_CAPACITY 1u
+#define GS_STATUS_SORT 2u
+
+typedef struct gs_camera {
+  float R[9];            /* world -> camera rotation, row-major (W in Sec. 4) */
+  float t[3];            /* world -> camera translation */
+  float fx, fy, cx, cy;  /* focal lengths and principal point, pixels */
+  int32_t width, height; /* image size, 1..GS_MAX_DIM */
+} gs_camera;
+
+/* The fixed numerical rules (App. C "Numerical stability"; Sec. 6) and the
+ * tuning knobs. gs_default_config fills the values the method uses. */
+typedef struct gs_config {
+  int32_t sh_degree;       /* 0..3 (Sec. 7.1: up to 4 bands) */
+  int32_t tile_size;       /* 8, 16 (the paper's value) or 32 pixels */
+  float near_z;            /* near cull on camera depth, 0.2 */
+  float sigma_extent;      /* a Gaussian touches a pixel iff m <= sigma_extent^2; 3 */
+  float alpha_min;         /* skip alpha below this, 1/255 */
+  float alpha_max;         /* clamp alpha to at most this, 0.99 */
+  float T_min;             /* stop before transmittance falls below this, 1e-4 */
+  float bg[3];             /* background colour added as T_final * bg */
+  int32_t sort_digit_bits; /* radix digit width of gs_sort: 8 */
+  int32_t reserved;        /* must be 0 */
+} gs_config;
+
+typedef struct gs_params {
+  const float* means;          /* [3][N] */
+  const float* log_scales;     /* [3][N]; scale = exp(log_scale) (Sec. 5.1) */
+  const float* quats;          /* [4][N] (r, i, j, k), normalised inside */
+  const float* opacity_logits; /* [N]; opacity = sigmoid(logit) (Sec. 5.1) */
+  const float* sh;             /* [K][3][N] */
+  int64_t n;                   /* N >= 0 */
+} gs_params;
+
+typedef struct gs_params_grad { /* same layouts as gs_params; overwritten */
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+} gs_params_grad;
+
+/* Per view and Gaussian (index v * N + g), written by gs_project:
+ *   depth_key     FP32 bit pattern of the camera-space depth (sort key low word)
+ *   tiles_touched tiles covered by the Gaussian's 3-sigma pixel box; 0 = culled
+ *   record        GS_RECORD_FLOATS floats:
+ *     [0] pixel box low corner  (i_lo | j_lo << 16) as int32 bits
+ *     [1] pixel box high corner (i_hi | j_hi << 16) as int32 bits
+ *     [2] u - i_lo, [3] v - j_lo   2D mean relative to the box corner
+ *     [4] w00, [5] w10, [6] w11    L^-1 with Sigma' = L L^T (Cholesky), so
+ *                                  m = (w00 dx)^2 + (w10 dx + w11 dy)^2
+ *     [7] opacity, [8..10] RGB colour, [11] camera depth (FP32)
+ * Valid only where tiles_touched > 0. */
+typedef struct gs_projected {
+  uint32_t* depth_key;     /* [V*N] */
+  int32_t* tiles_touched;  /* [V*N] */
+  float* record;           /* [V*N][GS_RECORD_FLOATS] */
+} gs_projected;
+
+/* Instance arrays (App. C "Sorting"): one (key, value) per Gaussian and overlapped
+ * tile. key = (global tile id << 32) | depth_key, value = v * N + g. gs_bin fills
+ * them unsorted; gs_sort leaves them sorted in keys/vals, ping-ponging through
+ * keys_alt/vals_alt. */
+typedef struct gs_instances {
+  uint64_t* keys;       /* [capacity] */
+  uint32_t* vals;       /* [capacity] */
+  uint64_t* keys_alt;   /* [capacity] */
+  uint32_t* vals_alt;   /* [capacity] */
+  int64_t capacity;     /* 0..GS_MAX_INSTANCES */
+  uint32_t* count;      /* device [1]: instance count M (the required count on overflow) */
+  uint32_t* status;     /* device [1]: GS_STATUS_* bits, OR-ed; the caller zeroes it */
+} gs_instances;
+
+/* Fill *cfg with the method's rules: SH degree 3, 16x16 tiles, near 0.2, 3 sigma,
+ * alpha in [1/255, 0.99], T_min 1e-4, black background, 8-bit sort digits. */
+void gs_default_config(gs_config* cfg);
+
+/* Global tile ids: view v owns ids [tile_offset[v], tile_offset[v+1]) laid out
+ * row-major over ceil(W/T) x ceil(H/T) tiles. Returns the total tile count
+ * (tile_offset[n_views]), or a negative GS_ERR_* on bad arguments.
+ * tile_offset may be NULL; otherwise it has n_views + 1 entries (host). */
+int64_t gs_tile_layout(const gs_camera* cams, int32_t n_views, int32_t tile_size,
+                       int64_t* tile_offset);
+
+/* Bits of the compacted sort key: 31 depth bits (depth > 0 keeps the sign bit 0)
+ * plus the bits of the largest global tile id. */
+int32_t gs_sort_key_bits(int64_t n_tiles_total);
+
+/* Project (Alg. 2 CullGaussian + ScreenspaceGaussians; Sec. 4 Eq. volume-render;
+ * Sec. 5 activations and SH colour). Reads params once and projects every
+ * Gaussian into every view: depth, near cull, Sigma' = J W Sigma W^T J^T, the
+ * 3-sigma pixel box, its Cholesky whitening, opacity and view-dependent colour.
+ * Arithmetic is FP64 inside; the outputs are FP32. */
+int gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views,
+               const gs_config* cfg, const gs_projected* out, gs_stream_t stream);
+
+/* Workspace bytes of gs_bin for V*N projected Gaussians. */
+size_t gs_bin_workspace_bytes(int64_t n_total);
+
+/* Bin (Alg. 2 CreateTiles + DuplicateWithKeys; App. C "Sorting"): exclusive scan
+ * of tiles_touched, then one (key, value) instance per Gaussian and covered tile,
+ * in Gaussian order. Writes the instance count to *inst->count; if it exceeds
+ * inst->capacity, ORs GS_STATUS_CAPACITY into *inst->status and writes nothing
+ * past capacity. n is N (per view). */
+int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
+           const gs_config* cfg, const gs_instances* inst, void* workspace,
+           size_t workspace_bytes, gs_stream_t stream);
+
+/* Workspace bytes of gs_sort. */
+size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total, const gs_config* cfg);
+
+/* Sort (Alg. 2 SortByKeys + IdentifyTileRanges; App. C): stable LSD radix sort of
+ * the M = min(*count, capacity) instances by key (onesweep: one histogram pass,
+ * then one pass per digit with decoupled look-back), then per global tile the
+ * range [start, end) of its instances, written to tile_ranges[t][2] (uint32).
+ * Ties in (tile, depth) keep Gaussian order. */
+int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
+            uint32_t* tile_ranges, void* workspace, size_t workspace_bytes,
+            gs_stream_t stream);
+
+/* Forward blend (Alg. 2 BlendInOrder; Eq. front-to-back; App. C rules): for every
+ * pixel of every view, front to back over its tile's instances: skip pixels
+ * outside the 3-sigma ellipse, alpha = min(alpha_max, o exp(-m/2)), skip
+ * alpha < alpha_min, stop before T (1 - alpha) < T_min, then add T_final * bg.
+ * Per view v the outputs start at pixel offset P_v = sum_{u<v} W_u H_u:
+ *   image    [3][H][W] planar FP32 at image + 3 P_v
+ *   T_final  [H][W] at T_final + P_v        final transmittance
+ *   last_idx [H][W] at last_idx + P_v       instance position of the last
+ *                                           blended Gaussian, -1 if none
+ * n is N (per view); instance values >= V*N are ignored. */
+int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
+                  const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                  const gs_config* cfg, float* image, float* T_final, int32_t* last_idx,
+                  int64_t n, gs_stream_t stream);
+
+/* Backward blend (Sec. 6: back to front from each pixel's last contributor,
+ * transmittance recovered by dividing the stored T_final by (1 - alpha); App. C):
+ * given dL/dimage in the image layout, accumulates per view and Gaussian the
+ * screen-space gradient record grad2d[v*N + g][9] =
+ *   d(u, v), d(w00, w10, w11), d(opacity), d(r, g, b).
+ * grad2d is zeroed by this call (in-stream) before accumulation. */
+int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
+                  const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                  const gs_config* cfg, const float* T_final, const int32_t* last_idx,
+                  const float* dL_dimage, float* grad2d, int64_t n, gs_stream_t stream);
+
+/* Projection backward (App. A chain rule, the quaternion normalisation, the
+ * activations, SH and its view direction): gradients of the raw parameters,
+ * summed over views, written (not accumulated) to *grads. */
+int gs_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views,
+                   const gs_config* cfg, const gs_projected* proj, const float* grad2d,
+                   const gs_params_grad* grads, gs_stream_t stream);
+
+/* Copy the device status word to the host after synchronising `stream`
+ * (the only synchronising call; not for use under graph capture). */
+int gs_read_status(const gs_instances* inst, uint32_t* status, uint32_t* count,
+                   gs_stream_t stream);
+
+const char* gs_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_MI355X_H */

@@ -1,0 +1,340 @@
+// gs_project / gs_project_bwd: per-Gaussian projection into every view and its
+// reverse-mode derivative. One thread per Gaussian; the parameters are read once
+// (coalesced SoA planes) and reused from registers for every view. FP64 inside:
+// the stage is HBM bound, and FP64 keeps the 2D mean and covariance far below
+// the FP32 error of the blend.
+#include "gs_device_math.h"
+
+namespace gs {
+
+constexpr int kProjBlock = 256;
+
+template <int DEG>
+__global__ void __launch_bounds__(kProjBlock)
+project_kernel(const float* __restrict__ means, const float* __restrict__ log_scales,
+               const float* __restrict__ quats, const float* __restrict__ logits,
+               const float* __restrict__ sh, int64_t n, ProjViews views, Rules rules,
+               uint32_t* __restrict__ depth_key, int32_t* __restrict__ tiles_touched,
+               float* __restrict__ record) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t g = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
+  if (g >= n) return;
+  const double x = means[g], y = means[n + g], z = means[2 * n + g];
+  const float ls0 = log_scales[g], ls1 = log_scales[n + g], ls2 = log_scales[2 * n + g];
+  const float q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
+  const float lg = logits[g];
+  float shc[K][3];
+  bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ls0) && isfinite(ls1) &&
+                isfinite(ls2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) &&
+                isfinite(lg);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      shc[k][ch] = sh[((int64_t)k * 3 + ch) * n + g];
+      finite = finite && isfinite(shc[k][ch]);
+    }
+  const double qn = sqrt((double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3);
+  const bool alive = finite && qn > 0.0;
+  double M[9];
+  double opac = 0.0;
+  if (alive) {
+    double R[9];
+    quat_to_rot(q0 / qn, q1 / qn, q2 / qn, q3 / qn, R);
+    const double s0 = exp((double)ls0), s1 = exp((double)ls1), s2 = exp((double)ls2);
+    for (int r = 0; r < 3; ++r) {
+      M[r * 3 + 0] = R[r * 3 + 0] * s0;
+      M[r * 3 + 1] = R[r * 3 + 1] * s1;
+      M[r * 3 + 2] = R[r * 3 + 2] * s2;
+    }
+    opac = 1.0 / (1.0 + exp(-(double)lg));
+  }
+  for (int v = 0; v < views.n_views; ++v) {
+    const int64_t idx = (int64_t)v * n + g;
+    const Cam& cam = views.cam[v];
+    ProjGeom p;
+    bool ok = alive;
+    if (ok) {
+      project_geometry(cam, rules, x, y, z, M, p);
+      ok = p.ok;
+    }
+    double rgb[3] = {0.0, 0.0, 0.0};
+    if (ok) {
+      // view direction: from the camera centre -R^T t to the mean
+      const double ccx = -((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1] + (double)cam.R[6] * cam.t[2]);
+      const double ccy = -((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1] + (double)cam.R[7] * cam.t[2]);
+      const double ccz = -((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1] + (double)cam.R[8] * cam.t[2]);
+      const double dx = x - ccx, dy = y - ccy, dz = z - ccz;
+      const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+      ok = dist > 0.0;
+      double Y[K];
+      sh_basis<DEG>(dx / dist, dy / dist, dz / dist, Y);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += (double)shc[k][ch] * Y[k];
+        rgb[ch] = fmax(acc + 0.5, 0.0);
+      }
+    }
+    if (!ok) {
+      tiles_touched[idx] = 0;
+      continue;
+    }
+    const int T = views.tile;
+    const int ntx = p.i_hi / T - p.i_lo / T + 1;
+    const int nty = p.j_hi / T - p.j_lo / T + 1;
+    tiles_touched[idx] = ntx * nty;
+    const float z32 = (float)p.tz;
+    depth_key[idx] = __float_as_uint(z32);
+    const double sa = sqrt(p.a), sd = sqrt(p.det);
+    float4* rec = reinterpret_cast<float4*>(record + idx * GS_RECORD_FLOATS);
+    rec[0] = make_float4(__int_as_float(p.i_lo | (p.j_lo << 16)), __int_as_float(p.i_hi | (p.j_hi << 16)),
+                         (float)(p.u - p.i_lo), (float)(p.v - p.j_lo));
+    rec[1] = make_float4((float)(1.0 / sa), (float)(-p.b / (sa * sd)), (float)(sa / sd), (float)opac);
+    rec[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], z32);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+
+template <int DEG>
+__global__ void __launch_bounds__(kProjBlock)
+project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ log_scales,
+                   const float* __restrict__ quats, const float* __restrict__ logits,
+                   const float* __restrict__ sh, int64_t n, ProjViews views, Rules rules,
+                   const int32_t* __restrict__ tiles_touched, const float* __restrict__ grad2d,
+                   float* __restrict__ d_means, float* __restrict__ d_log_scales,
+                   float* __restrict__ d_quats, float* __restrict__ d_logits,
+                   float* __restrict__ d_sh) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t g = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
+  if (g >= n) return;
+  double dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dqh[4] = {0, 0, 0, 0}, dop = 0.0;
+  double dshc[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) dshc[k][0] = dshc[k][1] = dshc[k][2] = 0.0;
+
+  bool any = false;
+  for (int v = 0; v < views.n_views; ++v) any = any || tiles_touched[(int64_t)v * n + g] > 0;
+  double qn = 0.0, qh[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0}, opac = 0.0;
+  if (any) {
+    const double x = means[g], y = means[n + g], z = means[2 * n + g];
+    const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
+    qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    qh[0] = q0 / qn; qh[1] = q1 / qn; qh[2] = q2 / qn; qh[3] = q3 / qn;
+    double R[9], M[9];
+    quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
+    s[0] = exp((double)log_scales[g]);
+    s[1] = exp((double)log_scales[n + g]);
+    s[2] = exp((double)log_scales[2 * n + g]);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * s[c];
+    opac = 1.0 / (1.0 + exp(-(double)logits[g]));
+    float shc[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) shc[k][ch] = sh[((int64_t)k * 3 + ch) * n + g];
+
+    double dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int v = 0; v < views.n_views; ++v) {
+      const int64_t idx = (int64_t)v * n + g;
+      if (tiles_touched[idx] <= 0) continue;
+      const Cam& cam = views.cam[v];
+      ProjGeom p;
+      project_geometry(cam, rules, x, y, z, M, p);
+      const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
+      const double du = gr[0], dv = gr[1], dw00 = gr[2], dw10 = gr[3], dw11 = gr[4];
+      dop += gr[5];
+      // whitening W = L^-1: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
+      const double a = p.a, b = p.b, c = p.c, det = p.det;
+      const double sa = sqrt(a), sd = sqrt(det);
+      const double isasd = 1.0 / (sa * sd), idet = 1.0 / det;
+      const double gA = dw00 * (-0.5 / (a * sa)) +
+                        dw10 * (0.5 * b / a * isasd + 0.5 * b * c * isasd * idet) +
+                        dw11 * (0.5 * isasd - 0.5 * sa * c * idet / sd);
+      const double gB = dw10 * (-isasd - b * b * isasd * idet) + dw11 * (sa * b * idet / sd);
+      const double gC = dw10 * (0.5 * b * sa * idet / sd) + dw11 * (-0.5 * a * sa * idet / sd);
+      // Sigma' = A A^T: dA0 = 2 gA A0 + gB A1, dA1 = gB A0 + 2 gC A1
+      double dA0[3], dA1[3];
+      for (int k = 0; k < 3; ++k) {
+        dA0[k] = 2.0 * gA * p.A0[k] + gB * p.A1[k];
+        dA1[k] = gB * p.A0[k] + 2.0 * gC * p.A1[k];
+      }
+      const double fx = cam.fx, fy = cam.fy, tx = p.tx, ty = p.ty, tz = p.tz;
+      const double iz = 1.0 / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+      const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
+      double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0, dWM[9];
+      for (int k = 0; k < 3; ++k) {
+        dJ00 += dA0[k] * p.WM[0 * 3 + k];
+        dJ02 += dA0[k] * p.WM[2 * 3 + k];
+        dJ11 += dA1[k] * p.WM[1 * 3 + k];
+        dJ12 += dA1[k] * p.WM[2 * 3 + k];
+        dWM[0 * 3 + k] = J00 * dA0[k];
+        dWM[1 * 3 + k] = J11 * dA1[k];
+        dWM[2 * 3 + k] = J02 * dA0[k] + J12 * dA1[k];
+      }
+      // WM = W M  ->  dM += W^T dWM
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          dM[i * 3 + j] += (double)cam.R[0 * 3 + i] * dWM[0 * 3 + j] +
+                           (double)cam.R[1 * 3 + i] * dWM[1 * 3 + j] +
+                           (double)cam.R[2 * 3 + i] * dWM[2 * 3 + j];
+      // camera-space mean through (u, v) and J
+      const double dtx = du * fx * iz + dJ02 * (-fx * iz2);
+      const double dty = dv * fy * iz + dJ12 * (-fy * iz2);
+      const double dtz = du * (-fx * tx * iz2) + dv * (-fy * ty * iz2) + dJ00 * (-fx * iz2) +
+                         dJ02 * (2.0 * fx * tx * iz3) + dJ11 * (-fy * iz2) +
+                         dJ12 * (2.0 * fy * ty * iz3);
+      for (int k = 0; k < 3; ++k)
+        dmu[k] += (double)cam.R[0 * 3 + k] * dtx + (double)cam.R[1 * 3 + k] * dty +
+                  (double)cam.R[2 * 3 + k] * dtz;
+      // colour: SH coefficients and the view direction
+      const double ccx = -((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1] + (double)cam.R[6] * cam.t[2]);
+      const double ccy = -((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1] + (double)cam.R[7] * cam.t[2]);
+      const double ccz = -((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1] + (double)cam.R[8] * cam.t[2]);
+      const double ex = x - ccx, ey = y - ccy, ez = z - ccz;
+      const double dist = sqrt(ex * ex + ey * ey + ez * ez);
+      const double dx = ex / dist, dy = ey / dist, dz = ez / dist;
+      double Y[K];
+      sh_basis<DEG>(dx, dy, dz, Y);
+      double dcol[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += (double)shc[k][ch] * Y[k];
+        dcol[ch] = (acc + 0.5 >= 0.0) ? (double)gr[6 + ch] : 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) dshc[k][ch] += Y[k] * dcol[ch];
+      }
+      if constexpr (DEG > 0) {
+        double G[K][3];
+        sh_basis_grad<DEG>(dx, dy, dz, G);
+        double ddir[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+          const double w = (double)shc[k][0] * dcol[0] + (double)shc[k][1] * dcol[1] +
+                           (double)shc[k][2] * dcol[2];
+          ddir[0] += w * G[k][0];
+          ddir[1] += w * G[k][1];
+          ddir[2] += w * G[k][2];
+        }
+        const double radial = dx * ddir[0] + dy * ddir[1] + dz * ddir[2];
+        dmu[0] += (ddir[0] - dx * radial) / dist;
+        dmu[1] += (ddir[1] - dy * radial) / dist;
+        dmu[2] += (ddir[2] - dz * radial) / dist;
+      }
+    }
+    // M = R diag(s): dR_ij = dM_ij s_j, ds_j = sum_i dM_ij R_ij
+    double dR[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        dR[i * 3 + j] = dM[i * 3 + j] * s[j];
+        ds[j] += dM[i * 3 + j] * R[i * 3 + j];
+      }
+    // derivative of Eq. (quat) with respect to (r, i, j, k)
+    const double r = qh[0], i = qh[1], j = qh[2], k = qh[3];
+    dqh[0] = 2.0 * (-k * dR[1] + j * dR[2] + k * dR[3] - i * dR[5] - j * dR[6] + i * dR[7]);
+    dqh[1] = 2.0 * (j * dR[1] + k * dR[2] + j * dR[3] - 2.0 * i * dR[4] - r * dR[5] + k * dR[6] +
+                    r * dR[7] - 2.0 * i * dR[8]);
+    dqh[2] = 2.0 * (-2.0 * j * dR[0] + i * dR[1] + r * dR[2] + i * dR[3] + k * dR[5] - r * dR[6] +
+                    k * dR[7] - 2.0 * j * dR[8]);
+    dqh[3] = 2.0 * (-2.0 * k * dR[0] - r * dR[1] + i * dR[2] + r * dR[3] - 2.0 * k * dR[4] +
+                    j * dR[5] + i * dR[6] + j * dR[7]);
+  }
+  // quaternion normalisation and activations
+  double dq[4] = {0, 0, 0, 0};
+  if (any) {
+    const double dotq = qh[0] * dqh[0] + qh[1] * dqh[1] + qh[2] * dqh[2] + qh[3] * dqh[3];
+    for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - qh[c] * dotq) / qn;
+  }
+  d_means[g] = (float)dmu[0];
+  d_means[n + g] = (float)dmu[1];
+  d_means[2 * n + g] = (float)dmu[2];
+  d_log_scales[g] = (float)(ds[0] * s[0]);
+  d_log_scales[n + g] = (float)(ds[1] * s[1]);
+  d_log_scales[2 * n + g] = (float)(ds[2] * s[2]);
+  for (int c = 0; c < 4; ++c) d_quats[(int64_t)c * n + g] = (float)dq[c];
+  d_logits[g] = (float)(dop * opac * (1.0 - opac));
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) d_sh[((int64_t)kk * 3 + ch) * n + g] = (float)dshc[kk][ch];
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" int gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views,
+                          const gs_config* cfg, const gs_projected* out, gs_stream_t stream) {
+  if (!params || !cams || !cfg || !out) return GS_ERR_ARG;
+  int rc = check_config(cfg);
+  if (rc != GS_OK) return rc;
+  if (params->n < 0) return GS_ERR_ARG;
+  if (params->n == 0) return GS_OK;
+  if (!params->means || !params->log_scales || !params->quats || !params->opacity_logits ||
+      !params->sh || !out->depth_key || !out->tiles_touched || !out->record)
+    return GS_ERR_ARG;
+  if (params->n * (int64_t)n_views >= ((int64_t)1 << 32)) return GS_ERR_UNSUPPORTED;
+  ProjViews pv;
+  rc = fill_proj_views(cams, n_views, cfg->tile_size, &pv);
+  if (rc != GS_OK) return rc;
+  const Rules rules = make_rules(cfg);
+  const int64_t n = params->n;
+  const dim3 grid((unsigned)((n + kProjBlock - 1) / kProjBlock));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+#define GS_LAUNCH_PROJ(D)                                                                     \
+  project_kernel<D><<<grid, kProjBlock, 0, s>>>(params->means, params->log_scales,            \
+                                                params->quats, params->opacity_logits,        \
+                                                params->sh, n, pv, rules, out->depth_key,     \
+                                                out->tiles_touched, out->record)
+  switch (cfg->sh_degree) {
+    case 0: GS_LAUNCH_PROJ(0); break;
+    case 1: GS_LAUNCH_PROJ(1); break;
+    case 2: GS_LAUNCH_PROJ(2); break;
+    default: GS_LAUNCH_PROJ(3); break;
+  }
+#undef GS_LAUNCH_PROJ
+  return launch_status();
+}
+
+extern "C" int gs_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views,
+                              const gs_config* cfg, const gs_projected* proj,
+                              const float* grad2d, const gs_params_grad* grads,
+                              gs_stream_t stream) {
+  if (!params || !cams || !cfg || !proj || !grads) return GS_ERR_ARG;
+  int rc = check_config(cfg);
+  if (rc != GS_OK) return rc;
+  if (params->n < 0) return GS_ERR_ARG;
+  if (params->n == 0) return GS_OK;
+  if (!params->means || !params->log_scales || !params->quats || !params->opacity_logits ||
+      !params->sh || !proj->tiles_touched || !grad2d || !grads->means || !grads->log_scales ||
+      !grads->quats || !grads->opacity_logits || !grads->sh)
+    return GS_ERR_ARG;
+  if (params->n * (int64_t)n_views >= ((int64_t)1 << 32)) return GS_ERR_UNSUPPORTED;
+  ProjViews pv;
+  rc = fill_proj_views(cams, n_views, cfg->tile_size, &pv);
+  if (rc != GS_OK) return rc;
+  const Rules rules = make_rules(cfg);
+  const int64_t n = params->n;
+  const dim3 grid((unsigned)((n + kProjBlock - 1) / kProjBlock));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+#define GS_LAUNCH_PBWD(D)                                                                     \
+  project_bwd_kernel<D><<<grid, kProjBlock, 0, s>>>(                                          \
+      params->means, params->log_scales, params->quats, params->opacity_logits, params->sh,   \
+      n, pv, rules, proj->tiles_touched, grad2d, grads->means, grads->log_scales,             \
+      grads->quats, grads->opacity_logits, grads->sh)
+  switch (cfg->sh_degree) {
+    case 0: GS_LAUNCH_PBWD(0); break;
+    case 1: GS_LAUNCH_PBWD(1); break;
+    case 2: GS_LAUNCH_PBWD(2); break;
+    default: GS_LAUNCH_PBWD(3); break;
+  }
+#undef GS_LAUNCH_PBWD
+  return launch_status();
+}

@@ -1,0 +1,360 @@
+// gs_render_fwd / gs_render_bwd: per-tile front-to-back blending (Alg. 2
+// BlendInOrder; Eq. front-to-back; App. C) and its back-to-front adjoint (Sec. 6).
+//
+// One workgroup per (view, tile); each 64-lane wave owns an 8x8 pixel block of
+// the tile and walks the tile's instance list on its own: it gathers 64 entries
+// (one per lane), keeps those whose 3-sigma pixel box meets its 8x8 block,
+// compacts them into its LDS slice with a ballot, and blends them from LDS
+// (broadcast reads). A wave stops as soon as all 64 of its pixels are saturated;
+// waves never wait for each other, so no workgroup barrier is needed.
+//
+// The backward pass walks the same list back to front from the wave's last
+// contributor, recovers T by dividing the stored final T by (1 - alpha), and
+// reduces the nine per-pixel partial gradients of each Gaussian over the wave
+// with DPP before one lane issues the global atomics.
+#include <algorithm>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+// Per-Gaussian LDS entry: geo = (box corner i_lo, j_lo as floats, mean - corner),
+// shape = (w00, w10, w11, opacity), col = (r, g, b, instance position bits).
+struct Eval {
+  float dx, dy, e0, e1, m, G, alpha;
+};
+
+// The one alpha evaluation used by both passes: identical instruction sequences
+// (the library is built with -ffp-contract=off), hence identical decisions.
+__device__ __forceinline__ void eval_alpha(const float4& geo, const float4& shape, float fpx,
+                                           float fpy, const Rules& r, Eval& e) {
+  e.dx = (fpx - geo.x) - geo.z;  // fpx - geo.x is exact: both are integers or half-integers
+  e.dy = (fpy - geo.y) - geo.w;
+  e.e0 = shape.x * e.dx;
+  e.e1 = fmaf(shape.y, e.dx, shape.z * e.dy);
+  e.m = fmaf(e.e0, e.e0, e.e1 * e.e1);
+  e.G = __expf(-0.5f * e.m);
+  e.alpha = fminf(r.alpha_max, shape.w * e.G);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+}
+
+struct WaveTile {
+  int v, tile, W, H, x0, y0, x1, y1, px, py;
+  uint32_t n_records;
+  bool inside;
+};
+
+template <int TS>
+__device__ __forceinline__ bool wave_tile(const TileViews& tv, WaveTile& w) {
+  w.tile = blockIdx.x;
+  w.n_records = tv.n_records;
+  w.v = view_of_tile(tv, w.tile);
+  const int lt = w.tile - tv.tile_offset[w.v];
+  const int tx = lt % tv.tiles_x[w.v], ty = lt / tv.tiles_x[w.v];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  constexpr int WX = TS / 8;
+  w.W = tv.W[w.v];
+  w.H = tv.H[w.v];
+  w.x0 = tx * TS + (wave % WX) * 8;
+  w.y0 = ty * TS + (wave / WX) * 8;
+  if (w.x0 >= w.W || w.y0 >= w.H) return false;
+  w.x1 = min(w.x0 + 7, w.W - 1);
+  w.y1 = min(w.y0 + 7, w.H - 1);
+  w.px = w.x0 + (lane & 7);
+  w.py = w.y0 + (lane >> 3);
+  w.inside = (w.px < w.W) && (w.py < w.H);
+  return true;
+}
+
+// Gather instance i (if i < end), test its box against the wave's block and
+// compact the kept ones into the wave's LDS slice. Returns the kept count.
+__device__ __forceinline__ int stage_batch(const float* __restrict__ record,
+                                           const uint32_t* __restrict__ vals, uint32_t i,
+                                           bool in_range, const WaveTile& w, float4* s_geo,
+                                           float4* s_shape, float4* s_col, uint32_t* s_gid) {
+  bool keep = false;
+  float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0;
+  uint32_t g = 0;
+  int ilo = 0, jlo = 0;
+  if (in_range) g = vals[i];
+  if (in_range && g < w.n_records) {
+    const float4* rec = reinterpret_cast<const float4*>(record + (size_t)g * GS_RECORD_FLOATS);
+    r0 = rec[0];
+    const int lo = __float_as_int(r0.x), hi = __float_as_int(r0.y);
+    ilo = lo & 0xFFFF;
+    jlo = (lo >> 16) & 0xFFFF;
+    const int ihi = hi & 0xFFFF, jhi = (hi >> 16) & 0xFFFF;
+    keep = (ilo <= w.x1) && (ihi >= w.x0) && (jlo <= w.y1) && (jhi >= w.y0);
+    if (keep) {
+      r1 = rec[1];
+      r2 = rec[2];
+    }
+  }
+  const uint64_t km = __ballot(keep);
+  if (keep) {
+    const int slot = __popcll(km & lanemask_lt());
+    s_geo[slot] = make_float4((float)ilo, (float)jlo, r0.z, r0.w);
+    s_shape[slot] = r1;
+    s_col[slot] = make_float4(r2.x, r2.y, r2.z, __uint_as_float(i));
+    if (s_gid) s_gid[slot] = g;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return __popcll(km);
+}
+
+template <int TS>
+__global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
+render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ ranges, TileViews tv, Rules rules,
+                  float* __restrict__ image, float* __restrict__ T_final,
+                  int32_t* __restrict__ last_idx) {
+  constexpr int WPT = (TS / 8) * (TS / 8);
+  __shared__ float4 s_geo[WPT][kWave];
+  __shared__ float4 s_shape[WPT][kWave];
+  __shared__ float4 s_col[WPT][kWave];
+  WaveTile w;
+  if (!wave_tile<TS>(tv, w)) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const uint32_t start = ranges[2 * w.tile], end = ranges[2 * w.tile + 1];
+  const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  int32_t last = -1;
+  bool done = !w.inside;
+  for (uint32_t base = start; base < end; base += kWave) {
+    if (__ballot(!done) == 0ull) break;
+    const uint32_t i = base + lane;
+    const int cnt = stage_batch(record, vals, i, i < end, w, s_geo[wave], s_shape[wave],
+                                s_col[wave], nullptr);
+    for (int k = 0; k < cnt; ++k) {
+      if (__ballot(!done) == 0ull) break;
+      const float4 geo = s_geo[wave][k];
+      const float4 shape = s_shape[wave][k];
+      if (!done) {
+        Eval e;
+        eval_alpha(geo, shape, fpx, fpy, rules, e);
+        if (e.m <= rules.ext2 && e.alpha >= rules.alpha_min) {
+          const float Tn = T * (1.0f - e.alpha);
+          if (Tn < rules.T_min) {
+            done = true;
+          } else {
+            const float4 col = s_col[wave][k];
+            const float wgt = T * e.alpha;
+            C0 = fmaf(wgt, col.x, C0);
+            C1 = fmaf(wgt, col.y, C1);
+            C2 = fmaf(wgt, col.z, C2);
+            T = Tn;
+            last = (int32_t)__float_as_uint(col.w);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (w.inside) {
+    const int64_t P = tv.pix_offset[w.v];
+    const int64_t HW = (int64_t)w.W * w.H;
+    const int64_t p = (int64_t)w.py * w.W + w.px;
+    float* img = image + 3 * P;
+    img[p] = fmaf(T, rules.bg[0], C0);
+    img[HW + p] = fmaf(T, rules.bg[1], C1);
+    img[2 * HW + p] = fmaf(T, rules.bg[2], C2);
+    T_final[P + p] = T;
+    last_idx[P + p] = last;
+  }
+}
+
+__device__ __forceinline__ int wave_max_int(int x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) x = max(x, __shfl_xor(x, d, kWave));
+  return x;
+}
+
+template <int TS>
+__global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
+render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ ranges, TileViews tv, Rules rules,
+                  const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
+                  const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
+  constexpr int WPT = (TS / 8) * (TS / 8);
+  __shared__ float4 s_geo[WPT][kWave];
+  __shared__ float4 s_shape[WPT][kWave];
+  __shared__ float4 s_col[WPT][kWave];
+  __shared__ uint32_t s_gid[WPT][kWave];
+  WaveTile w;
+  if (!wave_tile<TS>(tv, w)) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const uint32_t start = ranges[2 * w.tile];
+  const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
+  float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  int32_t last = -1;
+  if (w.inside) {
+    const int64_t P = tv.pix_offset[w.v];
+    const int64_t HW = (int64_t)w.W * w.H;
+    const int64_t p = (int64_t)w.py * w.W + w.px;
+    T = T_final[P + p];
+    last = last_idx[P + p];
+    const float* dimg = dL_dimage + 3 * P;
+    g0 = dimg[p];
+    g1 = dimg[HW + p];
+    g2 = dimg[2 * HW + p];
+  }
+  float B0 = T * rules.bg[0], B1 = T * rules.bg[1], B2 = T * rules.bg[2];
+  const int wave_last = wave_max_int(last);
+  if (wave_last < (int)start) return;  // no pixel of this wave blended anything
+  for (int64_t top = wave_last; top >= (int64_t)start; top -= kWave) {
+    const int64_t bot = max((int64_t)start, top - (kWave - 1));
+    const int64_t i = bot + lane;
+    const int cnt = stage_batch(record, vals, (uint32_t)i, i <= top, w, s_geo[wave],
+                                s_shape[wave], s_col[wave], s_gid[wave]);
+    for (int k = cnt - 1; k >= 0; --k) {
+      const float4 geo = s_geo[wave][k];
+      const float4 shape = s_shape[wave][k];
+      const float4 col = s_col[wave][k];
+      const int32_t pos = (int32_t)__float_as_uint(col.w);
+      float d_mx = 0.f, d_my = 0.f, d_w00 = 0.f, d_w10 = 0.f, d_w11 = 0.f, d_o = 0.f;
+      float d_r = 0.f, d_g = 0.f, d_b = 0.f;
+      bool contrib = false;
+      if (pos <= last) {
+        Eval e;
+        eval_alpha(geo, shape, fpx, fpy, rules, e);
+        if (e.m <= rules.ext2 && e.alpha >= rules.alpha_min) {
+          contrib = true;
+          const float inv = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+          T = T * inv;  // transmittance in front of this Gaussian
+          const float wgt = T * e.alpha;
+          d_r = wgt * g0;
+          d_g = wgt * g1;
+          d_b = wgt * g2;
+          const float dalpha = g0 * (T * col.x - B0 * inv) + g1 * (T * col.y - B1 * inv) +
+                               g2 * (T * col.z - B2 * inv);
+          B0 = fmaf(wgt, col.x, B0);
+          B1 = fmaf(wgt, col.y, B1);
+          B2 = fmaf(wgt, col.z, B2);
+          if (shape.w * e.G <= rules.alpha_max) {  // alpha not clamped
+            d_o = dalpha * e.G;
+            const float dm = -0.5f * dalpha * e.alpha;
+            const float t0 = 2.0f * dm * e.e0, t1 = 2.0f * dm * e.e1;
+            // m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = px - mean
+            d_mx = -(t0 * shape.x + t1 * shape.y);
+            d_my = -(t1 * shape.z);
+            d_w00 = t0 * e.dx;
+            d_w10 = t1 * e.dx;
+            d_w11 = t1 * e.dy;
+          }
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+        d_mx = wave_sum_to_lane63(d_mx);
+        d_my = wave_sum_to_lane63(d_my);
+        d_w00 = wave_sum_to_lane63(d_w00);
+        d_w10 = wave_sum_to_lane63(d_w10);
+        d_w11 = wave_sum_to_lane63(d_w11);
+        d_o = wave_sum_to_lane63(d_o);
+        d_r = wave_sum_to_lane63(d_r);
+        d_g = wave_sum_to_lane63(d_g);
+        d_b = wave_sum_to_lane63(d_b);
+        if (lane == kWave - 1) {
+          float* dst = grad2d + (size_t)s_gid[wave][k] * GS_GRAD2D_FLOATS;
+          atomicAdd(dst + 0, d_mx);
+          atomicAdd(dst + 1, d_my);
+          atomicAdd(dst + 2, d_w00);
+          atomicAdd(dst + 3, d_w10);
+          atomicAdd(dst + 4, d_w11);
+          atomicAdd(dst + 5, d_o);
+          atomicAdd(dst + 6, d_r);
+          atomicAdd(dst + 7, d_g);
+          atomicAdd(dst + 8, d_b);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_zero(float* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0.0f;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+static int render_common(const gs_projected* proj, const gs_instances* inst,
+                         const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                         const gs_config* cfg, int64_t n, TileViews* tv) {
+  if (!proj || !inst || !tile_ranges || !cams || !cfg || n < 0) return GS_ERR_ARG;
+  int rc = check_config(cfg);
+  if (rc != GS_OK) return rc;
+  rc = fill_tile_views(cams, n_views, cfg->tile_size, tv);
+  if (rc != GS_OK) return rc;
+  if (n * (int64_t)n_views >= ((int64_t)1 << 32)) return GS_ERR_UNSUPPORTED;
+  tv->n_records = (uint32_t)(n * n_views);
+  if (!proj->record || !inst->vals) return GS_ERR_ARG;
+  return GS_OK;
+}
+
+extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
+                             const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                             const gs_config* cfg, float* image, float* T_final, int32_t* last_idx,
+                             int64_t n, gs_stream_t stream) {
+  TileViews tv;
+  int rc = render_common(proj, inst, tile_ranges, cams, n_views, cfg, n, &tv);
+  if (rc != GS_OK) return rc;
+  if (!image || !T_final || !last_idx) return GS_ERR_ARG;
+  const Rules rules = make_rules(cfg);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)tv.tile_offset[n_views]);
+  switch (cfg->tile_size) {
+    case 8:
+      render_fwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+                                               image, T_final, last_idx);
+      break;
+    case 32:
+      render_fwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tv,
+                                                  rules, image, T_final, last_idx);
+      break;
+    default:
+      render_fwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+                                                 image, T_final, last_idx);
+      break;
+  }
+  return launch_status();
+}
+
+extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
+                             const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                             const gs_config* cfg, const float* T_final, const int32_t* last_idx,
+                             const float* dL_dimage, float* grad2d, int64_t n,
+                             gs_stream_t stream) {
+  TileViews tv;
+  int rc = render_common(proj, inst, tile_ranges, cams, n_views, cfg, n, &tv);
+  if (rc != GS_OK) return rc;
+  if (!T_final || !last_idx || !dL_dimage || !grad2d) return GS_ERR_ARG;
+  const Rules rules = make_rules(cfg);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t ng = n * (int64_t)n_views * GS_GRAD2D_FLOATS;
+  if (ng > 0)
+    fill_zero<<<dim3((unsigned)std::min<int64_t>((ng + 255) / 256, 8192)), 256, 0, s>>>(grad2d, ng);
+  const dim3 grid((unsigned)tv.tile_offset[n_views]);
+  switch (cfg->tile_size) {
+    case 8:
+      render_bwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+                                               T_final, last_idx, dL_dimage, grad2d);
+      break;
+    case 32:
+      render_bwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tv,
+                                                  rules, T_final, last_idx, dL_dimage, grad2d);
+      break;
+    default:
+      render_bwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+                                                 T_final, last_idx, dL_dimage, grad2d);
+      break;
+  }
+  return launch_status();
+}

@@ -1,0 +1,321 @@
+// gs_sort: stable LSD radix sort of the instance keys (Alg. 2 SortByKeys; App. C
+// "Sorting"; the paper uses a single GPU radix sort after Merrill and Grimshaw)
+// followed by IdentifyTileRanges.
+//
+// Onesweep structure (Adinets and Merrill, 2022): one histogram pass over the
+// keys computes the digit counts of every pass at once; then each digit pass is a
+// single launch in which a 256-thread block takes 4096 keys in ticket order,
+// ranks them in LDS (wave ballots find the lanes sharing a digit), publishes its
+// digit counts, resolves its global digit offsets by decoupled look-back over the
+// blocks before it, and scatters the keys, staged through LDS so the writes of a
+// digit run are contiguous.
+//
+// The sort key is compacted to (tile id << 31) | depth31: camera depths are
+// positive floats, so bit 31 of the depth word is always 0 and is not sorted on.
+#include <algorithm>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per block
+constexpr int kMaxPasses = 16;
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValueMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t compact_key(uint64_t k) {
+  return ((k >> 32) << 31) | (k & 0x7FFFFFFFull);
+}
+
+struct SortWs {
+  uint32_t* hist;      // [passes][256] digit counts, then their exclusive scan
+  uint32_t* ticket;    // [passes]
+  uint32_t* lookback;  // [passes][n_blocks][256]
+  int64_t n_blocks;
+};
+
+static SortWs carve(void* ws, int64_t capacity) {
+  SortWs w;
+  uint32_t* p = static_cast<uint32_t*>(ws);
+  w.n_blocks = (capacity + kSortTile - 1) / kSortTile;
+  if (w.n_blocks < 1) w.n_blocks = 1;
+  w.hist = p;
+  w.ticket = p + kMaxPasses * 256;
+  w.lookback = w.ticket + 64;
+  return w;
+}
+
+__global__ void __launch_bounds__(256)
+sort_init(SortWs w, int passes, const uint32_t* __restrict__ count, int64_t capacity) {
+  const int64_t M = min((int64_t)count[0], capacity);
+  const int64_t nb = (M + kSortTile - 1) / kSortTile;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < (int64_t)passes * 256; i += stride) w.hist[i] = 0;
+  for (int64_t i = t0; i < 64; i += stride) w.ticket[i] = 0;
+  for (int p = 0; p < passes; ++p) {
+    uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
+    for (int64_t i = t0; i < nb * 256; i += stride) lb[i] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+sort_histogram(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
+               int64_t capacity, int passes, int db, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t sh[kMaxPasses][256];
+  for (int i = threadIdx.x; i < kMaxPasses * 256; i += 256) (&sh[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t M = min((int64_t)count[0], capacity);
+  const uint64_t mask = (1ull << db) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
+    const uint64_t ck = compact_key(keys[i]);
+    for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(ck >> (p * db)) & mask], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * 256; i += 256) {
+    const uint32_t c = (&sh[0][0])[i];
+    if (c) atomicAdd(&hist[i], c);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+sort_scan_hist(uint32_t* __restrict__ hist, int passes) {
+  __shared__ uint32_t s[256];
+  const int t = threadIdx.x;
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t x = hist[p * 256 + t];
+    s[t] = x;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+      const uint32_t y = (t >= d) ? s[t - d] : 0u;
+      __syncthreads();
+      s[t] += y;
+      __syncthreads();
+    }
+    hist[p * 256 + t] = s[t] - x;
+    __syncthreads();
+  }
+}
+
+template <int DB>
+__global__ void __launch_bounds__(kSortBlock)
+sort_pass(const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+          uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+          const uint32_t* __restrict__ count, int64_t capacity, int shift,
+          const uint32_t* __restrict__ digit_start, uint32_t* __restrict__ lookback,
+          uint32_t* __restrict__ ticket, uint32_t* __restrict__ status) {
+  constexpr int RADIX = 1 << DB;
+  constexpr int WAVES = kSortBlock / kWave;
+  constexpr int WAVE_ITEMS = kSortTile / WAVES;
+  __shared__ uint64_t s_keys[kSortTile];
+  __shared__ uint32_t s_vals[kSortTile];
+  __shared__ uint32_t s_whist[WAVES][RADIX];
+  __shared__ uint32_t s_local_base[RADIX];
+  __shared__ uint32_t s_global_base[RADIX];
+  __shared__ uint32_t s_scan[kSortBlock];
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+  for (int i = tid; i < WAVES * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t M = min((int64_t)count[0], capacity);
+  if (tile * kSortTile >= M) return;  // uniform over the block
+
+  // load: wave w owns the contiguous run [tile*4096 + w*1024, +1024), round r lane l
+  const int64_t wbase = tile * kSortTile + (int64_t)wave * WAVE_ITEMS;
+  uint64_t k[kSortItems];
+  uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = wbase + (int64_t)r * kWave + lane;
+    const bool valid = i < M;
+    k[r] = valid ? keys_in[i] : ~0ull;
+    val[r] = valid ? vals_in[i] : 0u;
+    dig[r] = valid ? (uint32_t)((compact_key(k[r]) >> shift) & (RADIX - 1)) : (uint32_t)RADIX;
+  }
+  // rank in input order (round-major, then lane): stable
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = dig[r] < (uint32_t)RADIX;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+      const bool bit = (dig[r] >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    uint32_t base = 0;
+    if (valid) {
+      base = s_whist[wave][dig[r]];
+      rank[r] = base + (uint32_t)__popcll(peers & lt_mask);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // the highest lane of each peer group writes the new count
+    if (valid && (peers >> lane) == 1ull) s_whist[wave][dig[r]] = base + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+
+  // per digit: exclusive offsets of the waves, block total
+  uint32_t total = 0;
+  if (tid < RADIX) {
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t c = s_whist[w][tid];
+      s_whist[w][tid] = total;
+      total += c;
+    }
+  }
+  // decoupled look-back: thread d resolves digit d
+  if (tid < RADIX) {
+    uint32_t* mine = lookback + tile * RADIX + tid;
+    uint32_t excl = 0;
+    if (tile == 0) {
+      __hip_atomic_store(mine, kFlagInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(mine, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t t = tile - 1;
+      uint32_t spins = 0;
+      while (t >= 0) {
+        const uint32_t w = __hip_atomic_load(lookback + t * RADIX + tid, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t flag = w & ~kValueMask;
+        if (flag == 0) {
+          if (++spins > kSpinLimit) {  // never expected; bounded so the grid always drains
+            atomicOr(status, GS_STATUS_SORT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += w & kValueMask;
+        if (flag == kFlagInc) break;
+        --t;
+      }
+      __hip_atomic_store(mine, kFlagInc | ((excl + total) & kValueMask), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_global_base[tid] = digit_start[tid] + excl;
+  }
+  // block-local exclusive scan of the digit totals
+  s_scan[tid] = (tid < RADIX) ? total : 0u;
+  __syncthreads();
+  for (int d = 1; d < kSortBlock; d <<= 1) {
+    const uint32_t y = (tid >= d) ? s_scan[tid - d] : 0u;
+    __syncthreads();
+    s_scan[tid] += y;
+    __syncthreads();
+  }
+  if (tid < RADIX) s_local_base[tid] = s_scan[tid] - total;
+  __syncthreads();
+  // reorder through LDS into block-sorted order
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (dig[r] < (uint32_t)RADIX) {
+      const uint32_t pos = s_local_base[dig[r]] + s_whist[wave][dig[r]] + rank[r];
+      s_keys[pos] = k[r];
+      s_vals[pos] = val[r];
+    }
+  }
+  __syncthreads();
+  const int n_valid = (int)min((int64_t)kSortTile, M - tile * kSortTile);
+  for (int s = tid; s < n_valid; s += kSortBlock) {
+    const uint64_t kk = s_keys[s];
+    const uint32_t d = (uint32_t)((compact_key(kk) >> shift) & (RADIX - 1));
+    const uint32_t g = s_global_base[d] + ((uint32_t)s - s_local_base[d]);
+    keys_out[g] = kk;
+    vals_out[g] = s_vals[s];
+  }
+}
+
+// IdentifyTileRanges: [start, end) of every global tile by binary search of the
+// sorted keys (equivalent to comparing neighbouring tile ids; no zero-fill needed).
+__global__ void __launch_bounds__(256)
+sort_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count, int64_t capacity,
+            int64_t n_tiles, uint32_t* __restrict__ ranges) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t M = min((int64_t)count[0], capacity);
+  auto lower = [&](uint64_t key) {
+    int64_t lo = 0, hi = M;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (keys[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  ranges[2 * t] = (uint32_t)lower((uint64_t)t << 32);
+  ranges[2 * t + 1] = (uint32_t)lower((uint64_t)(t + 1) << 32);
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total,
+                                          const gs_config* cfg) {
+  if (capacity < 0 || !cfg || check_config(cfg) != GS_OK) return 0;
+  const int passes = sort_passes(n_tiles_total, cfg->sort_digit_bits);
+  int64_t nb = (capacity + kSortTile - 1) / kSortTile;
+  if (nb < 1) nb = 1;
+  return (size_t)(kMaxPasses * 256 + 64 + (int64_t)passes * nb * 256) * sizeof(uint32_t);
+}
+
+extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
+                       uint32_t* tile_ranges, void* workspace, size_t workspace_bytes,
+                       gs_stream_t stream) {
+  if (!inst || !cfg || !tile_ranges || !workspace || n_tiles_total < 1) return GS_ERR_ARG;
+  int rc = check_config(cfg);
+  if (rc != GS_OK) return rc;
+  if (!inst->keys || !inst->vals || !inst->keys_alt || !inst->vals_alt || !inst->count ||
+      !inst->status || inst->capacity < 0)
+    return GS_ERR_ARG;
+  if (inst->capacity > GS_MAX_INSTANCES) return GS_ERR_UNSUPPORTED;
+  if (n_tiles_total >= ((int64_t)1 << 31)) return GS_ERR_UNSUPPORTED;
+  if (workspace_bytes < gs_sort_workspace_bytes(inst->capacity, n_tiles_total, cfg)) return GS_ERR_ARG;
+  const int db = cfg->sort_digit_bits;
+  const int passes = sort_passes(n_tiles_total, db);
+  if (passes > kMaxPasses) return GS_ERR_UNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SortWs w = carve(workspace, inst->capacity);
+  const int64_t cap = inst->capacity;
+  sort_init<<<dim3((unsigned)std::min<int64_t>(std::max<int64_t>(w.n_blocks, 1), 1024)), 256, 0, s>>>(
+      w, passes, inst->count, cap);
+  // gs_bin leaves the unsorted instances where an even number of ping-pong passes
+  // ends in keys/vals
+  const bool odd = passes & 1;
+  uint64_t* kb[2] = {odd ? inst->keys_alt : inst->keys, odd ? inst->keys : inst->keys_alt};
+  uint32_t* vb[2] = {odd ? inst->vals_alt : inst->vals, odd ? inst->vals : inst->vals_alt};
+  if (cap > 0) {
+    const unsigned hb = (unsigned)std::min<int64_t>((cap + 4095) / 4096, 2048);
+    sort_histogram<<<dim3(hb), 256, 0, s>>>(kb[0], inst->count, cap, passes, db, w.hist);
+    sort_scan_hist<<<1, 256, 0, s>>>(w.hist, passes);
+    const dim3 grid((unsigned)w.n_blocks);
+    for (int p = 0; p < passes; ++p) {
+      const int src = p & 1, dst = src ^ 1;
+      uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
+#define GS_LAUNCH_PASS(D)                                                                       \
+  sort_pass<D><<<grid, kSortBlock, 0, s>>>(kb[src], vb[src], kb[dst], vb[dst], inst->count, cap, \
+                                           p * db, w.hist + p * 256, lb, w.ticket + p,          \
+                                           inst->status)
+      switch (db) {
+        case 4: GS_LAUNCH_PASS(4); break;
+        case 5: GS_LAUNCH_PASS(5); break;
+        case 6: GS_LAUNCH_PASS(6); break;
+        case 7: GS_LAUNCH_PASS(7); break;
+        default: GS_LAUNCH_PASS(8); break;
+      }
+#undef GS_LAUNCH_PASS
+    }
+  }
+  sort_ranges<<<dim3((unsigned)((n_tiles_total + 255) / 256)), 256, 0, s>>>(
+      inst->keys, inst->count, cap, n_tiles_total, tile_ranges);
+  return launch_status();
+}

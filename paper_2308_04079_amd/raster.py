@@ -1,0 +1,240 @@
+"""Python driver of the HIP rasterizer: buffers (torch device memory), streams, autograd.
+
+Argument marshalling only: every step of the forward and backward pass runs in
+libgs_mi355x.so. The stages follow Alg. 2 of Kerbl et al. (2023):
+gs_project -> gs_bin -> gs_sort -> gs_render_fwd, and backward
+gs_render_bwd -> gs_project_bwd (Sec. 6, App. A).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+
+
+@dataclasses.dataclass
+class GaussianParams:
+    """Raw Gaussian parameters, SoA float32 on the GPU (see include/gs.h for layouts)."""
+    means: torch.Tensor           # (3, N)
+    log_scales: torch.Tensor      # (3, N)
+    quats: torch.Tensor           # (4, N)
+    opacity_logits: torch.Tensor  # (N,)
+    sh: torch.Tensor              # (K, 3, N)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[1])
+
+    @property
+    def sh_degree(self) -> int:
+        return int(round(self.sh.shape[0] ** 0.5)) - 1
+
+    def c_struct(self) -> _lib.GsParams:
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            t = getattr(self, name)
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+        return _lib.GsParams(_lib.ptr(self.means), _lib.ptr(self.log_scales), _lib.ptr(self.quats),
+                             _lib.ptr(self.opacity_logits), _lib.ptr(self.sh), self.n)
+
+    @staticmethod
+    def from_numpy(scene, device="cuda") -> "GaussianParams":
+        def t(a):
+            return torch.from_numpy(a.astype("float32", copy=False)).contiguous().to(device)
+        return GaussianParams(t(scene.means), t(scene.log_scales), t(scene.quats),
+                              t(scene.opacity_logits), t(scene.sh))
+
+
+@dataclasses.dataclass
+class RenderState:
+    """Everything the forward pass leaves for the backward pass (and for inspection)."""
+    n: int
+    cams: list
+    cams_c: ctypes.Array
+    n_views: int
+    n_tiles: int
+    tile_offset: list
+    pix_offset: list
+    depth_key: torch.Tensor
+    tiles_touched: torch.Tensor
+    record: torch.Tensor
+    keys: torch.Tensor
+    vals: torch.Tensor
+    keys_alt: torch.Tensor
+    vals_alt: torch.Tensor
+    count: torch.Tensor
+    status: torch.Tensor
+    capacity: int
+    ranges: torch.Tensor
+    image: torch.Tensor       # flat: per view [3][H][W] at 3 * pix_offset[v]
+    T_final: torch.Tensor     # flat: per view [H][W] at pix_offset[v]
+    last_idx: torch.Tensor
+
+    def projected(self) -> _lib.GsProjected:
+        return _lib.GsProjected(_lib.ptr(self.depth_key), _lib.ptr(self.tiles_touched),
+                                _lib.ptr(self.record))
+
+    def instances(self) -> _lib.GsInstances:
+        return _lib.GsInstances(_lib.ptr(self.keys), _lib.ptr(self.vals), _lib.ptr(self.keys_alt),
+                                _lib.ptr(self.vals_alt), self.capacity, _lib.ptr(self.count),
+                                _lib.ptr(self.status))
+
+    def view_image(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        p = self.pix_offset[v]
+        return self.image[3 * p:3 * (p + c.width * c.height)].view(3, c.height, c.width)
+
+    def view_plane(self, buf: torch.Tensor, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        p = self.pix_offset[v]
+        return buf[p:p + c.width * c.height].view(c.height, c.width)
+
+    def read_status(self):
+        """(status bits, instance count); synchronises the current stream."""
+        st, ct = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        inst = self.instances()
+        _lib.lib().gs_read_status(ctypes.byref(inst), ctypes.byref(st), ctypes.byref(ct),
+                                  torch.cuda.current_stream().cuda_stream)
+        return int(st.value), int(ct.value)
+
+
+class Rasterizer:
+    """Forward and backward of the tile rasterizer over V >= 1 views per call.
+
+    capacity: instance capacity (grows automatically when ``check`` is on).
+    """
+
+    def __init__(self, sh_degree: int = 3, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
+                 capacity: int | None = None, growth: float = 1.25, sort_digit_bits: int = 8):
+        self.cfg = _lib.default_config(sh_degree=sh_degree, tile_size=tile_size, bg=bg,
+                                       sort_digit_bits=sort_digit_bits)
+        self.capacity = capacity
+        self.growth = growth
+
+    # -- forward -----------------------------------------------------------------
+    def render(self, params: GaussianParams, cams, check: bool = True) -> RenderState:
+        lib = _lib.lib()
+        if params.sh_degree != self.cfg.sh_degree:
+            raise ValueError(f"params carry SH degree {params.sh_degree}, config has "
+                             f"{self.cfg.sh_degree}")
+        cams = list(cams)
+        V = len(cams)
+        n = params.n
+        dev = params.means.device
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        cams_c = _lib.make_cameras(cams)
+        cfg = ctypes.byref(self.cfg)
+        toff = (ctypes.c_int64 * (V + 1))()
+        n_tiles = lib.gs_tile_layout(cams_c, V, self.cfg.tile_size, toff)
+        _lib.check("gs_tile_layout", 0 if n_tiles > 0 else int(n_tiles))
+        pix = [0]
+        for c in cams:
+            pix.append(pix[-1] + int(c.width) * int(c.height))
+
+        depth_key = torch.empty(max(1, V * n), dtype=torch.int32, device=dev)
+        tiles_touched = torch.zeros(max(1, V * n), dtype=torch.int32, device=dev)
+        record = torch.empty(max(1, V * n) * _lib.RECORD_FLOATS, dtype=torch.float32, device=dev)
+        pr = params.c_struct()
+        proj = _lib.GsProjected(_lib.ptr(depth_key), _lib.ptr(tiles_touched), _lib.ptr(record))
+        _lib.check("gs_project", lib.gs_project(ctypes.byref(pr), cams_c, V, cfg,
+                                                ctypes.byref(proj), stream))
+        cap = self.capacity if self.capacity is not None else max(1 << 16, 2 * n * V)
+        ranges = torch.empty(2 * n_tiles, dtype=torch.int32, device=dev)
+        image = torch.empty(3 * pix[-1], dtype=torch.float32, device=dev)
+        T_final = torch.empty(pix[-1], dtype=torch.float32, device=dev)
+        last_idx = torch.empty(pix[-1], dtype=torch.int32, device=dev)
+        bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n)), dtype=torch.uint8,
+                             device=dev)
+        while True:
+            cap = min(int(cap), _lib.MAX_INSTANCES)
+            keys = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+            vals = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            keys_alt = torch.empty_like(keys)
+            vals_alt = torch.empty_like(vals)
+            count = torch.zeros(1, dtype=torch.int32, device=dev)
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+            state = RenderState(n, cams, cams_c, V, int(n_tiles), list(toff), pix, depth_key,
+                                tiles_touched, record, keys, vals, keys_alt, vals_alt, count,
+                                status, cap, ranges, image, T_final, last_idx)
+            inst = state.instances()
+            _lib.check("gs_bin", lib.gs_bin(ctypes.byref(proj), n, cams_c, V, cfg,
+                                            ctypes.byref(inst), _lib.ptr(bin_ws),
+                                            bin_ws.numel(), stream))
+            sort_bytes = lib.gs_sort_workspace_bytes(cap, n_tiles, cfg)
+            sort_ws = torch.empty(max(1, sort_bytes), dtype=torch.uint8, device=dev)
+            _lib.check("gs_sort", lib.gs_sort(ctypes.byref(inst), n_tiles, cfg,
+                                              _lib.ptr(ranges), _lib.ptr(sort_ws),
+                                              sort_ws.numel(), stream))
+            _lib.check("gs_render_fwd", lib.gs_render_fwd(
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(ranges), cams_c, V, cfg,
+                _lib.ptr(image), _lib.ptr(T_final), _lib.ptr(last_idx), n, stream))
+            if not check:
+                break
+            st, ct = state.read_status()
+            if st & _lib.STATUS_CAPACITY:
+                if ct > _lib.MAX_INSTANCES:
+                    raise _lib.GsError("gs_bin", _lib.ERR_UNSUPPORTED)
+                cap = max(int(ct * self.growth) + 1, cap + 1)
+                continue
+            if st & _lib.STATUS_SORT:
+                raise _lib.GsError("gs_sort", _lib.ERR_SORT)
+            break
+        self.capacity = cap
+        return state
+
+    # -- backward ----------------------------------------------------------------
+    def backward(self, params: GaussianParams, state: RenderState, dL_dimage: torch.Tensor):
+        """Gradients of the raw parameters (dict of tensors shaped like ``params``)."""
+        lib = _lib.lib()
+        dev = params.means.device
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        cfg = ctypes.byref(self.cfg)
+        V, n = state.n_views, state.n
+        if dL_dimage.numel() != state.image.numel() or dL_dimage.dtype != torch.float32:
+            raise ValueError("dL_dimage must match the flat float32 image layout")
+        dL_dimage = dL_dimage.contiguous()
+        grad2d = torch.empty(max(1, V * n * _lib.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
+        proj = state.projected()
+        inst = state.instances()
+        _lib.check("gs_render_bwd", lib.gs_render_bwd(
+            ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(state.ranges), state.cams_c, V, cfg,
+            _lib.ptr(state.T_final), _lib.ptr(state.last_idx), _lib.ptr(dL_dimage),
+            _lib.ptr(grad2d), n, stream))
+        grads = {k: torch.empty_like(getattr(params, k))
+                 for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+        gp = _lib.GsParamsGrad(*(_lib.ptr(grads[k]) for k in
+                                 ("means", "log_scales", "quats", "opacity_logits", "sh")))
+        pr = params.c_struct()
+        _lib.check("gs_project_bwd", lib.gs_project_bwd(
+            ctypes.byref(pr), state.cams_c, V, cfg, ctypes.byref(proj), _lib.ptr(grad2d),
+            ctypes.byref(gp), stream))
+        return grads, grad2d
+
+
+class RasterizeFunction(torch.autograd.Function):
+    """Differentiable rasterization: returns the flat image of all views (see RenderState)."""
+
+    @staticmethod
+    def forward(ctx, rasterizer, cams, means, log_scales, quats, opacity_logits, sh):
+        params = GaussianParams(means.contiguous(), log_scales.contiguous(), quats.contiguous(),
+                                opacity_logits.contiguous(), sh.contiguous())
+        state = rasterizer.render(params, cams)
+        ctx.rasterizer = rasterizer
+        ctx.state = state
+        ctx.params = params
+        return state.image
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        grads, _ = ctx.rasterizer.backward(ctx.params, ctx.state, dL_dimage.float())
+        return (None, None, grads["means"], grads["log_scales"], grads["quats"],
+                grads["opacity_logits"], grads["sh"])
+
+
+def rasterize(rasterizer: Rasterizer, cams, means, log_scales, quats, opacity_logits, sh):
+    """Autograd entry point: flat image (per view [3][H][W], concatenated)."""
+    return RasterizeFunction.apply(rasterizer, list(cams), means, log_scales, quats,
+                                   opacity_logits, sh)

@@ -1,0 +1,92 @@
+"""The C ABI library loads on the CPU and exports every entry point include/gs.h declares.
+
+No compute call is made here (there is no GPU): only the host-side helpers and the
+argument checks that return before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(gs_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2308_04079_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libgs_mi355x.so is not built (run __graft_entry__.build())")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 13, names
+    h = L.lib()
+    for name in names:
+        assert hasattr(h, name), name
+        assert name in L.EXPORTS, f"{name} is not bound in _lib.EXPORTS"
+
+
+def test_binding_covers_only_declared_symbols(L):
+    assert set(L.EXPORTS) <= set(declared_functions())
+
+
+def test_struct_sizes_match_the_header_layout(L):
+    assert ctypes.sizeof(L.GsCamera) == 4 * 18
+    assert ctypes.sizeof(L.GsConfig) == 4 * 12
+    assert ctypes.sizeof(L.GsParams) == 8 * 6
+    assert ctypes.sizeof(L.GsInstances) == 8 * 7
+
+
+def test_default_config_is_the_papers_rules(L):
+    c = L.default_config()
+    assert (c.sh_degree, c.tile_size, c.sort_digit_bits) == (3, 16, 8)
+    assert abs(c.near_z - 0.2) < 1e-7 and c.sigma_extent == 3.0
+    assert abs(c.alpha_min - 1 / 255) < 1e-9 and abs(c.alpha_max - 0.99) < 1e-7
+    assert abs(c.T_min - 1e-4) < 1e-10 and list(c.bg) == [0.0, 0.0, 0.0]
+
+
+def test_tile_layout_and_key_bits(L):
+    import scenes
+    cams = [scenes.pinhole_camera(1920, 1080), scenes.pinhole_camera(37, 29)]
+    cc = L.make_cameras(cams)
+    off = (ctypes.c_int64 * 3)()
+    n = L.lib().gs_tile_layout(cc, 2, 16, off)
+    assert list(off) == [0, 120 * 68, 120 * 68 + 3 * 2] and n == off[2]
+    assert L.lib().gs_sort_key_bits(8160) == 31 + 13
+    assert L.lib().gs_sort_key_bits(64) == 31 + 6
+    assert L.lib().gs_sort_key_bits(1) == 31
+    assert L.lib().gs_tile_layout(cc, 2, 12, None) == L.ERR_ARG
+    assert L.lib().gs_tile_layout(cc, 0, 16, None) == L.ERR_ARG
+
+
+def test_host_argument_checks_return_before_any_launch(L):
+    import scenes
+    lib = L.lib()
+    cc = L.make_cameras([scenes.pinhole_camera(64, 64)])
+    cfg = L.default_config()
+    bad = L.default_config(sh_degree=5)
+    p = L.GsParams(0, 0, 0, 0, 0, 10)
+    proj = L.GsProjected(0, 0, 0)
+    assert lib.gs_project(ctypes.byref(p), cc, 1, ctypes.byref(bad), ctypes.byref(proj), None) == L.ERR_ARG
+    assert lib.gs_project(ctypes.byref(p), cc, 1, ctypes.byref(cfg), ctypes.byref(proj), None) == L.ERR_ARG
+    neg = L.GsParams(0, 0, 0, 0, 0, -1)
+    assert lib.gs_project(ctypes.byref(neg), cc, 1, ctypes.byref(cfg), ctypes.byref(proj), None) == L.ERR_ARG
+    many = L.make_cameras([scenes.pinhole_camera(8, 8)] * 33)
+    inst = L.GsInstances(0, 0, 0, 0, 0, 0, 0)
+    assert lib.gs_bin(ctypes.byref(proj), 1, many, 33, ctypes.byref(cfg), ctypes.byref(inst), None, 0, None) in (L.ERR_ARG, L.ERR_UNSUPPORTED)
+    huge = L.make_cameras([scenes.pinhole_camera(40000, 8)])
+    assert lib.gs_render_fwd(ctypes.byref(proj), ctypes.byref(inst), 1, huge, 1, ctypes.byref(cfg), 1, 1, 1, 1, None) == L.ERR_UNSUPPORTED
+    assert lib.gs_sort(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, 0, None) == L.ERR_ARG
+    assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) > (1 << 20) // 4096 * 6 * 1024
+    assert lib.gs_status_string(L.ERR_CAPACITY) == b"instance count exceeds capacity"

@@ -1,0 +1,231 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Bars: depth keys, pixel boxes, tile lists, sorted instances and tile ranges
+bit-exact (decisions within the oracle's margins excepted); images within 1e-4
+max-abs on unambiguous pixels; gradients within 1e-3 relative L2 per group.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle.adjoint import render_backward
+from oracle.gaussians import project
+from oracle.raster import render_tiles, tile_lists
+from oracle.rules import Rules
+from tests.gpu_common import (GROUPS, TOL_GRAD, TOL_IMAGE, decode_records, gpu_images,
+                              gpu_render, rel_l2, to_np)
+
+pytestmark = pytest.mark.gpu
+
+
+def small_cases():
+    return {
+        "small": scenes.workload("small"),
+        "ragged": (scenes.uniform_scene(700, 21, 2, (2.0, 8.0)), [scenes.pinhole_camera(77, 45)]),
+        "offcentre": (scenes.uniform_scene(900, 22, 3, (1.5, 9.0), xy_range=(-2, 2)),
+                      [scenes.look_at_camera([0.4, -0.3, -0.5], [0.0, 0.1, 5.0], 96, 64)]),
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_project_matches_oracle(name):
+    sc, cams = CASES[name]
+    _, _, state = gpu_render(sc, cams)
+    p = project(sc, cams[0])
+    g = decode_records(state, 0)
+    flagged = p.aabb_margin
+    assert np.array_equal(g["valid"] & ~flagged, p.valid & ~flagged)
+    ok = g["valid"] & p.valid
+    assert np.array_equal(g["zkey"][ok], p.zkey[ok])
+    for k in ("i_lo", "i_hi", "j_lo", "j_hi"):
+        assert np.array_equal(g[k][ok & ~flagged], getattr(p, k)[ok & ~flagged]), k
+    np.testing.assert_allclose(g["u"][ok], p.u[ok], rtol=0, atol=2e-5)
+    np.testing.assert_allclose(g["v"][ok], p.v[ok], rtol=0, atol=2e-5)
+    np.testing.assert_allclose(g["conic"][ok], p.conic[ok], rtol=2e-5,
+                               atol=2e-6 * np.abs(p.conic[ok]).max())
+    np.testing.assert_allclose(g["opacity"][ok], p.opacity[ok], rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(g["rgb"][ok], p.rgb[ok], rtol=0, atol=1e-6)
+
+
+def expected_sorted_instances(state, tile=16):
+    """Instances built in NumPy from the GPU's own projection, sorted by (key, value)."""
+    keys, vals = [], []
+    for v, cam in enumerate(state.cams):
+        g = decode_records(state, v)
+        tx_n = (cam.width + tile - 1) // tile
+        for i in np.nonzero(g["valid"])[0]:
+            for ty in range(g["j_lo"][i] // tile, g["j_hi"][i] // tile + 1):
+                for tx in range(g["i_lo"][i] // tile, g["i_hi"][i] // tile + 1):
+                    t = state.tile_offset[v] + ty * tx_n + tx
+                    keys.append((t << 32) | int(g["zkey"][i]))
+                    vals.append(v * state.n + i)
+    keys = np.array(keys, dtype=np.uint64)
+    vals = np.array(vals, dtype=np.int64)
+    order = np.lexsort((vals, keys))
+    return keys[order], vals[order]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sort_and_ranges_bit_exact(name):
+    sc, cams = CASES[name]
+    _, _, state = gpu_render(sc, cams)
+    M = int(to_np(state.count)[0])
+    ek, ev = expected_sorted_instances(state)
+    assert M == ek.size
+    gk = to_np(state.keys)[:M].view(np.uint64)
+    gv = to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(gk, ek)
+    assert np.array_equal(gv, ev)
+    rng = to_np(state.ranges).reshape(-1, 2).astype(np.int64)
+    tiles = (ek >> np.uint64(32)).astype(np.int64)
+    for t in range(state.n_tiles):
+        s, e = np.searchsorted(tiles, t), np.searchsorted(tiles, t, side="right")
+        assert (rng[t, 0], rng[t, 1]) == (s, e) or (s == e and rng[t, 0] == rng[t, 1])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tile_lists_match_oracle(name):
+    sc, cams = CASES[name]
+    _, _, state = gpu_render(sc, cams)
+    p = project(sc, cams[0])
+    tl = tile_lists(p)
+    rng = to_np(state.ranges).reshape(-1, 2).astype(np.int64)
+    vals = to_np(state.vals).astype(np.int64) & 0xFFFFFFFF
+    for t in range(tl.tiles_x * tl.tiles_y):
+        gids = vals[rng[t, 0]:rng[t, 1]]
+        oids = tl.ids[tl.start[t]:tl.start[t + 1]]
+        keep_g = gids[~p.aabb_margin[gids]]
+        keep_o = oids[~p.aabb_margin[oids]]
+        assert np.array_equal(keep_g, keep_o), t
+
+
+def compare_images(state, sc, cams, tiles=None, rules=Rules()):
+    worst = 0.0
+    for v, (img, T, gid) in enumerate(gpu_images(state)):
+        p = project(sc, cams[v], rules)
+        ref = render_tiles(p, rules, tiles=tiles)
+        m = ref.done & ~ref.ambiguous
+        assert ref.ambiguous[ref.done].mean() < 1e-3
+        err = np.abs(img - ref.color)[m]
+        worst = max(worst, float(err.max()) if err.size else 0.0)
+        assert worst <= TOL_IMAGE, (v, worst)
+        np.testing.assert_allclose(T[m], ref.T_final[m], rtol=2e-3, atol=1e-6)
+        assert np.array_equal(gid[m], ref.last_id[m])
+    return worst
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_image_matches_oracle(name):
+    sc, cams = CASES[name]
+    _, _, state = gpu_render(sc, cams)
+    compare_images(state, sc, cams)
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_tile_size_does_not_change_image(tile):
+    sc, cams = CASES["ragged"]
+    _, _, s16 = gpu_render(sc, cams)
+    _, _, st = gpu_render(sc, cams, tile_size=tile)
+    a, b = gpu_images(s16)[0], gpu_images(st)[0]
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    compare_images(st, sc, cams, rules=Rules(tile=tile))
+
+
+def backward_case(sc, cams, seed, tiles=None):
+    import torch
+    rast, params, state = gpu_render(sc, cams)
+    cam = cams[0]
+    ref = render_tiles(project(sc, cam), tiles=tiles)
+    w = np.random.default_rng(seed).standard_normal((cam.height, cam.width, 3))
+    w *= (ref.done & ~ref.ambiguous)[..., None]
+    dimg = torch.from_numpy(np.ascontiguousarray(w.transpose(2, 0, 1)).astype(np.float32))
+    grads, grad2d = rast.backward(params, state, dimg.reshape(-1).cuda())
+    torch.cuda.synchronize()
+    gref, acc, p = render_backward(sc, cam, w, tiles=tiles)
+    return grads, grad2d, gref, acc, p
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_matches_oracle(name):
+    sc, cams = CASES[name]
+    grads, grad2d, gref, acc, p = backward_case(sc, cams, 5)
+    g2 = to_np(grad2d).reshape(-1, 9)[:sc.n].astype(np.float64)
+    ok = p.valid
+    assert rel_l2(g2[ok, 0], acc["u"][ok]) <= TOL_GRAD
+    assert rel_l2(g2[ok, 1], acc["v"][ok]) <= TOL_GRAD
+    assert rel_l2(g2[ok, 5], acc["opacity"][ok]) <= TOL_GRAD
+    assert rel_l2(g2[ok, 6:9], acc["rgb"][ok]) <= TOL_GRAD
+    for k in GROUPS:
+        a = to_np(grads[k]).astype(np.float64)
+        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+
+
+def test_single720_sampled_tiles_forward_and_backward():
+    sc, cams = scenes.workload("single720")
+    rng = np.random.default_rng(7)
+    tl_x, tl_y = 80, 45
+    tiles = np.sort(rng.choice(tl_x * tl_y, 120, replace=False))
+    _, _, state = gpu_render(sc, cams)
+    compare_images(state, sc, cams, tiles=tiles)
+    grads, _, gref, _, _ = backward_case(sc, cams, 6, tiles=tiles)
+    for k in GROUPS:
+        a = to_np(grads[k]).astype(np.float64)
+        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+
+
+def test_multiview_batch_equals_single_views():
+    sc = scenes.clustered_scene(20_000, 31, 3)
+    cams = scenes.orbit_cameras(3, 31, resolutions=((96, 64), (64, 48), (128, 72)))
+    _, _, batch = gpu_render(sc, cams)
+    bimgs = gpu_images(batch)
+    for v, cam in enumerate(cams):
+        _, _, single = gpu_render(sc, [cam])
+        s = gpu_images(single)[0]
+        np.testing.assert_array_equal(bimgs[v][0], s[0])
+        np.testing.assert_array_equal(bimgs[v][1], s[1])
+        np.testing.assert_array_equal(bimgs[v][2], s[2])
+    compare_images(batch, sc, cams)
+
+
+def test_empty_and_fully_culled_scenes():
+    cam = scenes.pinhole_camera(40, 24)
+    empty = scenes.uniform_scene(0, 1, 0)
+    _, _, st = gpu_render(empty, [cam])
+    img, T, gid = gpu_images(st)[0]
+    assert np.all(img == 0) and np.all(T == 1) and np.all(gid == -1)
+    behind = scenes.uniform_scene(200, 2, 0, (-5.0, -1.0))
+    _, _, st = gpu_render(behind, [cam])
+    img, T, gid = gpu_images(st)[0]
+    assert int(to_np(st.count)[0]) == 0 and np.all(img == 0) and np.all(gid == -1)
+
+
+def test_capacity_overflow_is_reported_and_recovered():
+    from paper_2308_04079_amd import GaussianParams, Rasterizer
+    sc, cams = CASES["small"]
+    params = GaussianParams.from_numpy(sc, "cuda")
+    rast = Rasterizer(sh_degree=0, capacity=16)
+    state = rast.render(params, cams, check=False)
+    st, ct = state.read_status()
+    assert st & 1 and ct > 16
+    state = rast.render(params, cams)        # grows the capacity and re-runs
+    assert rast.capacity >= ct
+    compare_images(state, sc, cams)
+
+
+def test_degenerate_gaussians_do_not_poison_the_image():
+    sc = scenes.uniform_scene(300, 41, 1, (2.0, 6.0))
+    sc.quats[:, :10] = 0.0                    # zero quaternion: culled
+    sc.means[0, 10:20] = np.nan               # non-finite: culled
+    sc.log_scales[:, 20:30] = -30.0           # vanishing scale: culled (empty box or det)
+    cams = [scenes.pinhole_camera(64, 64)]
+    _, _, state = gpu_render(sc, cams)
+    img = gpu_images(state)[0][0]
+    assert np.isfinite(img).all()
+    assert np.all(to_np(state.tiles_touched)[:20] == 0)
+    compare_images(state, sc, cams)
