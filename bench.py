@@ -1,0 +1,324 @@
+"""Benchmark: 1080p forward+backward views/s at 3M Gaussians, batched vs per-view.
+
+One step = the whole hot path over one batch of views: project -> bin -> sort ->
+blend forward -> L1 loss gradient -> blend backward -> projection backward, on
+seeded synthetic inputs resident in HBM (3M Gaussians of the clustered-scene
+generator, SH degree 3, four 1920x1080 orbit cameras; targets rendered once from a
+jittered copy of the scene). ``value`` is the batched rate (all views of a step in
+one call per stage); the same step done one view at a time is reported beside it.
+
+Prints one JSON line (rank 0). Runs on one GPU: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector issue rate without packed-FP32 instructions: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; an FMA counts as two flops.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--views", type=int, default=4)
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2308_04079_amd import GaussianParams, Rasterizer
+    from paper_2308_04079_amd.raster import l1_loss_grad
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    t0 = time.time()
+    sc = scenes.clustered_scene(args.n, 4, 3)
+    cams = scenes.orbit_cameras(args.views, 4, resolutions=((1920, 1080),))
+    target_sc = scenes.jitter_means(sc, 4)
+    params = GaussianParams.from_numpy(sc, dev)
+    tparams = GaussianParams.from_numpy(target_sc, dev)
+    del target_sc
+    log(f"[bench] scene ready in {time.time() - t0:.1f}s: N={sc.n}, {len(cams)} views")
+
+    rast = Rasterizer(sh_degree=3)
+    tstate = rast.render(tparams, cams)             # sizes the capacity and renders targets
+    target = tstate.image.clone()
+    del tstate, tparams
+    probe = rast.render(params, cams)
+    st, count = probe.read_status()
+    rast.capacity = int(count * 1.15) + 4096
+    del probe
+    V = len(cams)
+    zero_loss = torch.zeros(V, dtype=torch.float32, device=dev)
+
+    def step(rs, cam_list, tgt, ev=None):
+        def mark(name):
+            if ev is not None:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                ev.append((name, e))
+        mark("start")
+        state = rs.render(params, cam_list, check=False)
+        mark("forward")
+        loss = zero_loss[:len(cam_list)].clone()
+        dL = l1_loss_grad(state, tgt, loss)
+        mark("loss")
+        grads, _ = rs.backward(params, state, dL)
+        mark("backward")
+        return state, grads, loss
+
+    # per-stage timing uses events between the library calls of one extra step
+    for _ in range(args.warmup):
+        state, grads, loss = step(rast, cams, target)
+    torch.cuda.synchronize()
+    st, count = state.read_status()
+    assert st == 0, f"device status {st} after warm-up"
+    log(f"[bench] warm-up done: M={count} instances for {V} views")
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        state, grads, loss = step(rast, cams, target)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    st, _ = state.read_status()
+    assert st == 0, f"device status {st} in the timed region"
+    ms_per_step = (t_end - t_start) * 1000.0 / args.steps
+    views_per_s = V * args.steps / (t_end - t_start)
+    log(f"[bench] batched: {ms_per_step:.2f} ms/step, {views_per_s:.1f} views/s")
+
+    # kernel-level timing of the dominant kernels, with events on the launch stream
+    stages = time_stages(rast, params, cams, target, args.steps, zero_loss)
+    log("[bench] stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stages["ms"].items()))
+
+    per_view = None
+    if not args.no_per_view:
+        prast = Rasterizer(sh_degree=3, capacity=rast.capacity)
+        tviews = [target[3 * state.pix_offset[v]:3 * state.pix_offset[v + 1]] for v in range(V)]
+        for _ in range(args.warmup):
+            for v in range(V):
+                step(prast, [cams[v]], tviews[v])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            for v in range(V):
+                step(prast, [cams[v]], tviews[v])
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        per_view = V * args.steps / (b - a)
+        log(f"[bench] per-view: {per_view:.1f} views/s")
+
+    roof = roofline(stages, state, count, sc.n, V)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(log)
+
+    out = {
+        "metric": "1080p fwd+bwd views/sec at 3M Gaussians, batched vs per-view, <=1e-4 image err",
+        "value": round(views_per_s, 3),
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"clustered scene, {sc.n} Gaussians, SH3, {V}x1920x1080 orbit "
+                               "views per step, fwd+bwd with L1 loss, batched (one call per stage)",
+                   "gaussians": sc.n, "views_per_step": V, "width": 1920, "height": 1080,
+                   "tile": 16, "sort_digit_bits": 8, "instances": count},
+        "per_view_value": None if per_view is None else round(per_view, 3),
+        "stage_ms": {k: round(v, 4) for k, v in stages["ms"].items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def time_stages(rast, params, cams, target, steps, zero_loss):
+    """Average duration of each library call over `steps` steps, HIP events on the stream."""
+    import ctypes
+
+    import torch
+
+    from paper_2308_04079_amd import _lib
+    lib = _lib.lib()
+    names = ["project", "bin", "sort", "render_fwd", "loss", "render_bwd", "project_bwd"]
+    acc = {k: 0.0 for k in names}
+    for _ in range(steps):
+        st = rast.render(params, cams, check=False)
+        # re-issue each stage on the same buffers, bracketed by events
+        stream = torch.cuda.current_stream().cuda_stream
+        cfg = ctypes.byref(rast.cfg)
+        proj, inst = st.projected(), st.instances()
+        pr = params.c_struct()
+        V, n = st.n_views, st.n
+        bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n)), dtype=torch.uint8,
+                             device="cuda")
+        sort_ws = torch.empty(max(1, lib.gs_sort_workspace_bytes(st.capacity, st.n_tiles, cfg)),
+                              dtype=torch.uint8, device="cuda")
+        dL = torch.empty_like(st.image)
+        loss = zero_loss[:V].clone()
+        grad2d = torch.zeros(V * n * _lib.GRAD2D_FLOATS, dtype=torch.float32, device="cuda")
+        grads = {k: torch.empty_like(getattr(params, k))
+                 for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+        gp = _lib.GsParamsGrad(*(_lib.ptr(grads[k]) for k in
+                                 ("means", "log_scales", "quats", "opacity_logits", "sh")))
+        calls = [
+            ("project", lambda: lib.gs_project(ctypes.byref(pr), st.cams_c, V, cfg,
+                                               ctypes.byref(proj), stream)),
+            ("bin", lambda: lib.gs_bin(ctypes.byref(proj), n, st.cams_c, V, cfg,
+                                       ctypes.byref(inst), _lib.ptr(bin_ws), bin_ws.numel(),
+                                       stream)),
+            ("sort", lambda: lib.gs_sort(ctypes.byref(inst), st.n_tiles, cfg, _lib.ptr(st.ranges),
+                                         _lib.ptr(sort_ws), sort_ws.numel(), stream)),
+            ("render_fwd", lambda: lib.gs_render_fwd(
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), st.cams_c, V, cfg,
+                _lib.ptr(st.image), _lib.ptr(st.T_final), _lib.ptr(st.last_idx), n, stream)),
+            ("loss", lambda: lib.gs_loss_l1(_lib.ptr(st.image), _lib.ptr(target), st.cams_c, V,
+                                            _lib.ptr(dL), _lib.ptr(loss), stream)),
+            ("render_bwd", lambda: lib.gs_render_bwd(
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), st.cams_c, V, cfg,
+                _lib.ptr(st.T_final), _lib.ptr(st.last_idx), _lib.ptr(dL), _lib.ptr(grad2d), n,
+                stream)),
+            ("project_bwd", lambda: lib.gs_project_bwd(ctypes.byref(pr), st.cams_c, V, cfg,
+                                                       ctypes.byref(proj), _lib.ptr(grad2d),
+                                                       ctypes.byref(gp), stream)),
+        ]
+        evs = []
+        for name, fn in calls:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            rc = fn()
+            b.record()
+            assert rc == 0, (name, rc)
+            evs.append((name, a, b))
+        torch.cuda.synchronize()
+        for name, a, b in evs:
+            acc[name] += a.elapsed_time(b)
+    st_last = st
+    return {"ms": {k: v / steps for k, v in acc.items()}, "state": st_last}
+
+
+def roofline(stages, state, count, n, V):
+    """Roofline of the dominant kernel: the blend backward (VALU bound), with its
+    algorithmic work counted from the forward state."""
+    import torch
+    ms = stages["ms"]
+    dom = max(("render_fwd", "render_bwd", "project", "project_bwd", "sort"), key=lambda k: ms[k])
+    st = stages["state"]
+    # E' = sum over pixels of the list entries at or before the pixel's last contributor
+    ranges = st.ranges.view(-1, 2).long()
+    evals = 0
+    for v in range(st.n_views):
+        cam = st.cams[v]
+        T = 16
+        tx = (cam.width + T - 1) // T
+        last = st.view_plane(st.last_idx, v).long()
+        ys = torch.arange(cam.height, device=last.device) // T
+        xs = torch.arange(cam.width, device=last.device) // T
+        tile = st.tile_offset[v] + ys[:, None] * tx + xs[None, :]
+        start = ranges[tile, 0]
+        evals += int(torch.clamp(last - start + 1, min=0).sum().item())
+    if dom == "render_bwd":
+        flops_per_eval = BWD_FLOPS_PER_EVAL
+    elif dom == "render_fwd":
+        flops_per_eval = FWD_FLOPS_PER_EVAL
+    else:
+        flops_per_eval = None
+    if flops_per_eval is not None:
+        achieved = evals * flops_per_eval / (ms[dom] * 1e-3) / 1e12
+        return {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "units": {"evaluations": evals, "flops_per_evaluation": flops_per_eval}}
+    # HBM-bound stages: algorithmic bytes
+    K = 16
+    per = {"project": (4 * (11 + 3 * K) + 56 * V), "project_bwd": (4 * (11 + 3 * K) * 2 + 36 * V)}
+    b = per.get(dom, 24) * (n if dom in per else count)
+    achieved = b / (ms[dom] * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+
+
+# Algorithmic FP32 flops of one (pixel, Gaussian) evaluation as the method states
+# it (FMA = 2): forward = offset (4) + Mahalanobis distance (8) + exp argument and
+# exp (2) + alpha (2) + three threshold tests (3) + T' (2) + colour (7) = 28;
+# backward adds the T recovery (2), colour and alpha gradients (15), the
+# opacity/mean/conic gradients (14) and the back-to-front accumulator (6) = 65.
+FWD_FLOPS_PER_EVAL = 28
+BWD_FLOPS_PER_EVAL = 65
+
+
+def cpu_baseline(log):
+    """The FP64 oracle timed on a bounded sample of one view of the same workload."""
+    import numpy as np
+
+    import scenes
+    from oracle.adjoint import blend_backward, empty_acc, project_backward
+    from oracle.gaussians import project
+    from oracle.raster import tile_lists, tile_pixels
+    from oracle.rules import Rules
+
+    sc = scenes.clustered_scene(3_000_000, 4, 3)
+    cam = scenes.orbit_cameras(1, 4, resolutions=((1920, 1080),))[0]
+    r = Rules()
+    t = time.perf_counter()
+    p = project(sc, cam, r)
+    t_proj = time.perf_counter() - t
+    t = time.perf_counter()
+    tl = tile_lists(p, r)
+    t_lists = time.perf_counter() - t
+    n_tiles = tl.tiles_x * tl.tiles_y
+    rng = np.random.default_rng(0)
+    sample = rng.choice(n_tiles, 16, replace=False)
+    acc = empty_acc(p.n)
+    w = rng.standard_normal((cam.height, cam.width, 3))
+    t = time.perf_counter()
+    for tt in sample:
+        px, py = tile_pixels(int(tt), tl, cam.width, cam.height, r.tile)
+        ids = tl.ids[tl.start[tt]:tl.start[tt + 1]]
+        blend_backward(p, ids, px, py, w[py, px], r, acc)
+    t_tiles = time.perf_counter() - t
+    t = time.perf_counter()
+    project_backward(sc, p, acc)
+    t_pbwd = time.perf_counter() - t
+    per_view_s = t_proj + t_lists + t_tiles * n_tiles / len(sample) + t_pbwd
+    log(f"[bench] oracle: project {t_proj:.1f}s lists {t_lists:.1f}s "
+        f"{len(sample)} tiles fwd+bwd {t_tiles:.1f}s project_bwd {t_pbwd:.1f}s "
+        f"-> {per_view_s:.0f}s per view")
+    return {"value": round(1.0 / per_view_s, 6), "unit": "views/s", "cores": 1, "kind": "oracle",
+            "sample": f"one 1920x1080 view of the 3M-Gaussian workload: full projection, tile "
+                      f"lists and projection backward, fwd+bwd blend of {len(sample)} of "
+                      f"{n_tiles} tiles scaled to the whole frame; single-threaded NumPy FP64"}
+
+
+if __name__ == "__main__":
+    main()

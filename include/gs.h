@@ -222,6 +222,15 @@ int gs_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_vie
                    const gs_config* cfg, const gs_projected* proj, const float* grad2d,
                    const gs_params_grad* grads, gs_stream_t stream);
 
+/* L1 photometric loss of Sec. 5.1 (the L1 term of L = (1 - lambda) L1 +
+ * lambda D-SSIM), per view the mean over 3 H W values of |image - target|:
+ * writes dL/dimage = sign(image - target) / (3 H W) (sign(0) = 0) in the image
+ * layout and, if loss is not NULL, ADDS each view's loss to loss[v] (device,
+ * caller zeroes it). image and target are device arrays in the gs_render_fwd
+ * image layout. */
+int gs_loss_l1(const float* image, const float* target, const gs_camera* cams, int32_t n_views,
+               float* dL_dimage, float* loss, gs_stream_t stream);
+
 /* Copy the device status word to the host after synchronising `stream`
  * (the only synchronising call; not for use under graph capture). */
 int gs_read_status(const gs_instances* inst, uint32_t* status, uint32_t* count,

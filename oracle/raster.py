@@ -118,7 +118,7 @@ def blend(proj, ids: np.ndarray, px: np.ndarray, py: np.ndarray,
         amb |= inside & (np.abs(alpha - rules.alpha_min) < rules.margin_alpha * rules.alpha_min)
         take = inside & (alpha >= rules.alpha_min)
         Tn = T * (1.0 - alpha)
-        tol = (n_blend + 8) * rules.margin_T_per_step * rules.T_min
+        tol = (n_blend + 4) * rules.margin_T_per_step * rules.T_min
         amb |= take & (np.abs(Tn - rules.T_min) < tol)
         stop = take & (Tn < rules.T_min)
         done |= stop

@@ -26,9 +26,15 @@ class Rules:
     alpha_max: float = 0.99
     T_min: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
-    # decision margins used to flag pixels whose result may legitimately differ
-    # between FP32 and FP64 evaluation (relative widths around each threshold)
+    # Decision margins: a pixel is "ambiguous" when one of its threshold decisions
+    # lies so close to the threshold that an FP32 evaluation may legitimately take
+    # the other branch. Each width is about 10x an FP32 error bound of the quantity:
+    #   m      ~ 1e-6 relative (the position stored to FP32 relative to a nearby
+    #          integer corner, a few roundings of terms <= 9)
+    #   alpha  ~ 5e-6 relative (m error / 2 plus the exponential's error)
+    #   T'     ~ (k + 4) * 6e-8 relative after k blended factors
+    #   bounds ~ 1e-7 px (FP64 projection evaluated in a different order)
     margin_m: float = 1e-5        # |m - 9| < margin_m * 9
-    margin_alpha: float = 1e-4    # |alpha - 1/255| < margin_alpha / 255
-    margin_T_per_step: float = 2e-6   # |T' - 1e-4| < (k + 8) * this * 1e-4 after k blends
+    margin_alpha: float = 5e-5    # |alpha - 1/255| < margin_alpha / 255
+    margin_T_per_step: float = 6e-7   # |T' - 1e-4| < (k + 4) * this * 1e-4 after k blends
     margin_px: float = 1e-6       # AABB bound within this many pixels of an integer

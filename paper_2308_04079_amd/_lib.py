@@ -89,6 +89,8 @@ EXPORTS = {
     "gs_project_bwd": (ctypes.c_int, [P(GsParams), P(GsCamera), ctypes.c_int32, P(GsConfig),
                                       P(GsProjected), ctypes.c_void_p, P(GsParamsGrad),
                                       ctypes.c_void_p]),
+    "gs_loss_l1": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, P(GsCamera), ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gs_read_status": (ctypes.c_int, [P(GsInstances), P(ctypes.c_uint32), P(ctypes.c_uint32),
                                       ctypes.c_void_p]),
     "gs_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -276,9 +276,35 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(256) fill_zero(float* __restrict__ p, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0.0f;
+// L1 loss gradient: one thread per pixel of the concatenated views.
+__global__ void __launch_bounds__(256)
+loss_l1_kernel(const float* __restrict__ image, const float* __restrict__ target, TileViews tv,
+               float* __restrict__ dL, float* __restrict__ loss) {
+  __shared__ float s_part[4];
+  const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = tv.pix_offset[tv.n_views];
+  // blocks never straddle views: the grid is laid out per view (blockIdx.y = view)
+  const int v = blockIdx.y;
+  const int64_t HW = tv.pix_offset[v + 1] - tv.pix_offset[v];
+  float part = 0.0f;
+  if (pix < HW) {
+    const float inv = 1.0f / (3.0f * (float)HW);
+    const int64_t base = 3 * tv.pix_offset[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t k = base + c * HW + pix;
+      const float d = image[k] - target[k];
+      dL[k] = (d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f));
+      part += fabsf(d) * inv;
+    }
+  }
+  (void)total;
+  if (loss) {
+    part = wave_sum_to_lane63(part);
+    if (__lane_id() == kWave - 1) s_part[threadIdx.x / kWave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss + v, s_part[0] + s_part[1] + s_part[2] + s_part[3]);
+  }
 }
 
 }  // namespace gs
@@ -327,6 +353,21 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
   return launch_status();
 }
 
+extern "C" int gs_loss_l1(const float* image, const float* target, const gs_camera* cams,
+                          int32_t n_views, float* dL_dimage, float* loss, gs_stream_t stream) {
+  if (!image || !target || !dL_dimage) return GS_ERR_ARG;
+  TileViews tv;
+  int rc = fill_tile_views(cams, n_views, 16, &tv);
+  if (rc != GS_OK) return rc;
+  int64_t max_hw = 0;
+  for (int v = 0; v < n_views; ++v)
+    max_hw = std::max<int64_t>(max_hw, tv.pix_offset[v + 1] - tv.pix_offset[v]);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  loss_l1_kernel<<<dim3((unsigned)((max_hw + 255) / 256), (unsigned)n_views), 256, 0, s>>>(
+      image, target, tv, dL_dimage, loss);
+  return launch_status();
+}
+
 extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
                              const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
                              const gs_config* cfg, const float* T_final, const int32_t* last_idx,
@@ -338,9 +379,6 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
   if (!T_final || !last_idx || !dL_dimage || !grad2d) return GS_ERR_ARG;
   const Rules rules = make_rules(cfg);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int64_t ng = n * (int64_t)n_views * GS_GRAD2D_FLOATS;
-  if (ng > 0)
-    fill_zero<<<dim3((unsigned)std::min<int64_t>((ng + 255) / 256, 8192)), 256, 0, s>>>(grad2d, ng);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
   switch (cfg->tile_size) {
     case 8:

@@ -196,7 +196,7 @@ class Rasterizer:
         if dL_dimage.numel() != state.image.numel() or dL_dimage.dtype != torch.float32:
             raise ValueError("dL_dimage must match the flat float32 image layout")
         dL_dimage = dL_dimage.contiguous()
-        grad2d = torch.empty(max(1, V * n * _lib.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
+        grad2d = torch.zeros(max(1, V * n * _lib.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
         proj = state.projected()
         inst = state.instances()
         _lib.check("gs_render_bwd", lib.gs_render_bwd(
@@ -232,6 +232,16 @@ class RasterizeFunction(torch.autograd.Function):
         grads, _ = ctx.rasterizer.backward(ctx.params, ctx.state, dL_dimage.float())
         return (None, None, grads["means"], grads["log_scales"], grads["quats"],
                 grads["opacity_logits"], grads["sh"])
+
+
+def l1_loss_grad(state: RenderState, target: torch.Tensor, loss: torch.Tensor | None = None):
+    """dL/dimage of the per-view mean L1 loss (flat image layout); adds the losses to ``loss``."""
+    dL = torch.empty_like(state.image)
+    stream = torch.cuda.current_stream(state.image.device).cuda_stream
+    _lib.check("gs_loss_l1", _lib.lib().gs_loss_l1(
+        _lib.ptr(state.image), _lib.ptr(target), state.cams_c, state.n_views, _lib.ptr(dL),
+        _lib.ptr(loss), stream))
+    return dL
 
 
 def rasterize(rasterizer: Rasterizer, cams, means, log_scales, quats, opacity_logits, sh):

@@ -58,14 +58,18 @@ def expected_sorted_instances(state, tile=16):
     for v, cam in enumerate(state.cams):
         g = decode_records(state, v)
         tx_n = (cam.width + tile - 1) // tile
-        for i in np.nonzero(g["valid"])[0]:
-            for ty in range(g["j_lo"][i] // tile, g["j_hi"][i] // tile + 1):
-                for tx in range(g["i_lo"][i] // tile, g["i_hi"][i] // tile + 1):
-                    t = state.tile_offset[v] + ty * tx_n + tx
-                    keys.append((t << 32) | int(g["zkey"][i]))
-                    vals.append(v * state.n + i)
-    keys = np.array(keys, dtype=np.uint64)
-    vals = np.array(vals, dtype=np.int64)
+        ids = np.nonzero(g["valid"])[0]
+        tx0, tx1 = g["i_lo"][ids] // tile, g["i_hi"][ids] // tile
+        ty0, ty1 = g["j_lo"][ids] // tile, g["j_hi"][ids] // tile
+        w = tx1 - tx0 + 1
+        cnt = w * (ty1 - ty0 + 1)
+        own = np.repeat(np.arange(ids.size), cnt)
+        local = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        t = state.tile_offset[v] + (ty0[own] + local // w[own]) * tx_n + tx0[own] + local % w[own]
+        keys.append((t.astype(np.uint64) << np.uint64(32)) | g["zkey"][ids][own].astype(np.uint64))
+        vals.append(v * state.n + ids[own])
+    keys = np.concatenate(keys) if keys else np.zeros(0, np.uint64)
+    vals = np.concatenate(vals).astype(np.int64) if vals else np.zeros(0, np.int64)
     order = np.lexsort((vals, keys))
     return keys[order], vals[order]
 
@@ -81,11 +85,15 @@ def test_sort_and_ranges_bit_exact(name):
     gv = to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF
     assert np.array_equal(gk, ek)
     assert np.array_equal(gv, ev)
+    check_ranges(state, ek)
+
+
+def check_ranges(state, ek):
     rng = to_np(state.ranges).reshape(-1, 2).astype(np.int64)
     tiles = (ek >> np.uint64(32)).astype(np.int64)
-    for t in range(state.n_tiles):
-        s, e = np.searchsorted(tiles, t), np.searchsorted(tiles, t, side="right")
-        assert (rng[t, 0], rng[t, 1]) == (s, e) or (s == e and rng[t, 0] == rng[t, 1])
+    t = np.arange(state.n_tiles)
+    assert np.array_equal(rng[:, 0], np.searchsorted(tiles, t))
+    assert np.array_equal(rng[:, 1], np.searchsorted(tiles, t, side="right"))
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -229,3 +237,21 @@ def test_degenerate_gaussians_do_not_poison_the_image():
     assert np.isfinite(img).all()
     assert np.all(to_np(state.tiles_touched)[:20] == 0)
     compare_images(state, sc, cams)
+
+
+def test_l1_loss_gradient():
+    import torch
+    from paper_2308_04079_amd.raster import l1_loss_grad
+    sc = scenes.uniform_scene(500, 51, 1, (2.0, 6.0))
+    cams = [scenes.pinhole_camera(40, 30), scenes.pinhole_camera(23, 17)]
+    _, _, state = gpu_render(sc, cams)
+    target = torch.rand_like(state.image)
+    target[:7] = state.image[:7]                      # exact ties give a zero gradient
+    loss = torch.zeros(2, device="cuda")
+    dL = to_np(l1_loss_grad(state, target, loss)).astype(np.float64)
+    img, tgt = to_np(state.image).astype(np.float64), to_np(target).astype(np.float64)
+    for v, cam in enumerate(cams):
+        sl = slice(3 * state.pix_offset[v], 3 * state.pix_offset[v + 1])
+        k = 3 * cam.width * cam.height
+        np.testing.assert_allclose(dL[sl], np.sign(img[sl] - tgt[sl]) / k, rtol=1e-6, atol=0)
+        np.testing.assert_allclose(to_np(loss)[v], np.abs(img[sl] - tgt[sl]).mean(), rtol=1e-5)
