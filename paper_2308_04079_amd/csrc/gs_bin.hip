@@ -88,43 +88,63 @@ bin_scan_sums(uint32_t* __restrict__ sums, int64_t n_blocks, int64_t capacity,
   }
 }
 
+// Load-balanced expansion: the block's 4096 counts are scanned in LDS, then each
+// thread produces output instances o = tid, tid + 256, ... of the block's range,
+// finding its Gaussian by binary search over the LDS prefix sums. Writes are
+// contiguous across the block.
 __global__ void __launch_bounds__(kBinBlock)
 bin_duplicate(const int32_t* __restrict__ touched, const uint32_t* __restrict__ depth_key,
               const float* __restrict__ record, int64_t n, int64_t total_items, TileViews tv,
               const uint32_t* __restrict__ block_offsets, int64_t capacity,
               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_off[kBinTile + 1];
   __shared__ uint32_t s4[kBinBlock / kWave];
-  // thread t owns the 16 consecutive items [base + 16 t, base + 16 t + 16)
-  const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
-  int32_t cnt[kBinItems];
-  uint32_t local = 0;
+  const int64_t base = (int64_t)blockIdx.x * kBinTile;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    const int64_t i = base + j;
-    cnt[j] = (i < total_items) ? max(touched[i], 0) : 0;
-    local += (uint32_t)cnt[j];
+    const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
+    s_off[j * kBinBlock + threadIdx.x] = (i < total_items) ? (uint32_t)max(touched[i], 0) : 0u;
+  }
+  __syncthreads();
+  // thread t scans the 16 consecutive counts [16 t, 16 t + 16)
+  uint32_t c[kBinItems], local = 0;
+#pragma unroll
+  for (int j = 0; j < kBinItems; ++j) {
+    c[j] = s_off[threadIdx.x * kBinItems + j];
+    local += c[j];
   }
   uint32_t tot;
-  uint32_t off = block_offsets[blockIdx.x] + block_excl_scan(local, s4, &tot);
-  const int T = tv.tile;
+  uint32_t run = block_excl_scan(local, s4, &tot);
+#pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    if (cnt[j] == 0) continue;
-    const int64_t i = base + j;
+    s_off[threadIdx.x * kBinItems + j] = run;
+    run += c[j];
+  }
+  if (threadIdx.x == 0) s_off[kBinTile] = tot;
+  __syncthreads();
+  const uint32_t out0 = block_offsets[blockIdx.x];
+  const int T = tv.tile;
+  for (uint32_t o = threadIdx.x; o < tot; o += kBinBlock) {
+    const uint64_t dst = (uint64_t)out0 + o;
+    if (dst >= (uint64_t)capacity) break;   // o only grows
+    // largest j with s_off[j] <= o (counts of zero give equal neighbours: take the last)
+    int lo = 0, hi = kBinTile - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= o) lo = mid; else hi = mid - 1;
+    }
+    const int64_t i = base + lo;
+    const uint32_t k = o - s_off[lo];
     const int v = (int)(i / n);
-    const int4 lohi = *reinterpret_cast<const int4*>(record + i * GS_RECORD_FLOATS);
+    const int2 lohi = *reinterpret_cast<const int2*>(record + i * GS_RECORD_FLOATS);
     const int ilo = lohi.x & 0xFFFF, jlo = (lohi.x >> 16) & 0xFFFF;
-    const int ihi = lohi.y & 0xFFFF, jhi = (lohi.y >> 16) & 0xFFFF;
-    const int tx0 = ilo / T, tx1 = ihi / T, ty0 = jlo / T, ty1 = jhi / T;
-    const uint64_t dk = depth_key[i];
-    const int toff = tv.tile_offset[v], tpr = tv.tiles_x[v];
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if ((int64_t)off < capacity) {
-          keys[off] = ((uint64_t)(uint32_t)(toff + ty * tpr + tx) << 32) | dk;
-          vals[off] = (uint32_t)i;
-        }
-        ++off;
-      }
+    const int ihi = lohi.y & 0xFFFF;
+    const int tx0 = ilo / T, ty0 = jlo / T;
+    const uint32_t wdt = (uint32_t)(ihi / T - tx0 + 1);
+    const uint32_t ty = (uint32_t)ty0 + k / wdt, tx = (uint32_t)tx0 + k % wdt;
+    keys[dst] = ((uint64_t)(uint32_t)(tv.tile_offset[v] + ty * tv.tiles_x[v] + tx) << 32) |
+                (uint64_t)depth_key[i];
+    vals[dst] = (uint32_t)i;
   }
 }
 

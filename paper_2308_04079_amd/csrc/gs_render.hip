@@ -131,27 +131,24 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
     const int cnt = stage_batch(record, vals, i, i < end, w, s_geo[wave], s_shape[wave],
                                 s_col[wave], nullptr);
     for (int k = 0; k < cnt; ++k) {
-      if (__ballot(!done) == 0ull) break;
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
-      if (!done) {
-        Eval e;
-        eval_alpha(geo, shape, fpx, fpy, rules, e);
-        if (e.m <= rules.ext2 && e.alpha >= rules.alpha_min) {
-          const float Tn = T * (1.0f - e.alpha);
-          if (Tn < rules.T_min) {
-            done = true;
-          } else {
-            const float4 col = s_col[wave][k];
-            const float wgt = T * e.alpha;
-            C0 = fmaf(wgt, col.x, C0);
-            C1 = fmaf(wgt, col.y, C1);
-            C2 = fmaf(wgt, col.z, C2);
-            T = Tn;
-            last = (int32_t)__float_as_uint(col.w);
-          }
-        }
-      }
+      const float4 col = s_col[wave][k];
+      Eval e;
+      eval_alpha(geo, shape, fpx, fpy, rules, e);
+      // branch-free: every lane evaluates, the decisions select what is kept
+      const bool take = !done && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min);
+      const float Tn = T * (1.0f - e.alpha);
+      const bool stop = take && (Tn < rules.T_min);
+      const bool blend = take && !stop;
+      const float wgt = blend ? T * e.alpha : 0.0f;
+      C0 = fmaf(wgt, col.x, C0);
+      C1 = fmaf(wgt, col.y, C1);
+      C2 = fmaf(wgt, col.z, C2);
+      T = blend ? Tn : T;
+      last = blend ? (int32_t)__float_as_uint(col.w) : last;
+      done = done || stop;
+      if ((k & 7) == 7 && __ballot(!done) == 0ull) break;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -172,6 +169,39 @@ __device__ __forceinline__ int wave_max_int(int x) {
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) x = max(x, __shfl_xor(x, d, kWave));
   return x;
+}
+
+// Sum over the 16 lanes of each DPP row; the row sum lands in every lane of the row.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, true));
+  return v;
+}
+
+// Reduce nine per-lane values over the wave and leave value k's wave total in
+// lanes k, k + 16, k + 32, k + 48 (k < 9): row sums by DPP, a lane-select so that
+// in-row position k carries value k, then two cross-row exchanges of that one value.
+__device__ __forceinline__ float wave_reduce9_transposed(float a0, float a1, float a2, float a3,
+                                                         float a4, float a5, float a6, float a7,
+                                                         float a8) {
+  a0 = row_sum16(a0); a1 = row_sum16(a1); a2 = row_sum16(a2);
+  a3 = row_sum16(a3); a4 = row_sum16(a4); a5 = row_sum16(a5);
+  a6 = row_sum16(a6); a7 = row_sum16(a7); a8 = row_sum16(a8);
+  const int k = __lane_id() & 15;
+  float v = a8;
+  v = (k == 7) ? a7 : v;
+  v = (k == 6) ? a6 : v;
+  v = (k == 5) ? a5 : v;
+  v = (k == 4) ? a4 : v;
+  v = (k == 3) ? a3 : v;
+  v = (k == 2) ? a2 : v;
+  v = (k == 1) ? a1 : v;
+  v = (k == 0) ? a0 : v;
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
+  return v;
 }
 
 template <int TS>
@@ -216,80 +246,52 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       const float4 shape = s_shape[wave][k];
       const float4 col = s_col[wave][k];
       const int32_t pos = (int32_t)__float_as_uint(col.w);
-      float d_mx = 0.f, d_my = 0.f, d_w00 = 0.f, d_w10 = 0.f, d_w11 = 0.f, d_o = 0.f;
-      float d_r = 0.f, d_g = 0.f, d_b = 0.f;
-      bool contrib = false;
-      if (pos <= last) {
-        Eval e;
-        eval_alpha(geo, shape, fpx, fpy, rules, e);
-        if (e.m <= rules.ext2 && e.alpha >= rules.alpha_min) {
-          contrib = true;
-          const float inv = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-          T = T * inv;  // transmittance in front of this Gaussian
-          const float wgt = T * e.alpha;
-          d_r = wgt * g0;
-          d_g = wgt * g1;
-          d_b = wgt * g2;
-          const float dalpha = g0 * (T * col.x - B0 * inv) + g1 * (T * col.y - B1 * inv) +
-                               g2 * (T * col.z - B2 * inv);
-          B0 = fmaf(wgt, col.x, B0);
-          B1 = fmaf(wgt, col.y, B1);
-          B2 = fmaf(wgt, col.z, B2);
-          if (shape.w * e.G <= rules.alpha_max) {  // alpha not clamped
-            d_o = dalpha * e.G;
-            const float dm = -0.5f * dalpha * e.alpha;
-            const float t0 = 2.0f * dm * e.e0, t1 = 2.0f * dm * e.e1;
-            // m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = px - mean
-            d_mx = -(t0 * shape.x + t1 * shape.y);
-            d_my = -(t1 * shape.z);
-            d_w00 = t0 * e.dx;
-            d_w10 = t1 * e.dx;
-            d_w11 = t1 * e.dy;
-          }
-        }
-      }
+      Eval e;
+      eval_alpha(geo, shape, fpx, fpy, rules, e);
+      // branch-free: non-contributing lanes add zeros and keep their state
+      const bool contrib = (pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min);
+      const float inv = contrib ? __builtin_amdgcn_rcpf(1.0f - e.alpha) : 1.0f;
+      T = T * inv;  // transmittance in front of this Gaussian
+      const float wgt = contrib ? T * e.alpha : 0.0f;
+      const float d_r = wgt * g0, d_g = wgt * g1, d_b = wgt * g2;
+      float dalpha = g0 * (T * col.x - B0 * inv) + g1 * (T * col.y - B1 * inv) +
+                     g2 * (T * col.z - B2 * inv);
+      B0 = fmaf(wgt, col.x, B0);
+      B1 = fmaf(wgt, col.y, B1);
+      B2 = fmaf(wgt, col.z, B2);
+      // alpha = min(alpha_max, o G): no gradient through a clamped alpha
+      dalpha = (contrib && shape.w * e.G <= rules.alpha_max) ? dalpha : 0.0f;
+      const float d_o = dalpha * e.G;
+      const float dm = -0.5f * dalpha * e.alpha;
+      const float t0 = 2.0f * dm * e.e0, t1 = 2.0f * dm * e.e1;
+      // m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = pixel - mean
+      const float d_mx = -(t0 * shape.x + t1 * shape.y);
+      const float d_my = -(t1 * shape.z);
+      const float d_w00 = t0 * e.dx, d_w10 = t1 * e.dx, d_w11 = t1 * e.dy;
       if (__ballot(contrib) != 0ull) {
-        d_mx = wave_sum_to_lane63(d_mx);
-        d_my = wave_sum_to_lane63(d_my);
-        d_w00 = wave_sum_to_lane63(d_w00);
-        d_w10 = wave_sum_to_lane63(d_w10);
-        d_w11 = wave_sum_to_lane63(d_w11);
-        d_o = wave_sum_to_lane63(d_o);
-        d_r = wave_sum_to_lane63(d_r);
-        d_g = wave_sum_to_lane63(d_g);
-        d_b = wave_sum_to_lane63(d_b);
-        if (lane == kWave - 1) {
-          float* dst = grad2d + (size_t)s_gid[wave][k] * GS_GRAD2D_FLOATS;
-          atomicAdd(dst + 0, d_mx);
-          atomicAdd(dst + 1, d_my);
-          atomicAdd(dst + 2, d_w00);
-          atomicAdd(dst + 3, d_w10);
-          atomicAdd(dst + 4, d_w11);
-          atomicAdd(dst + 5, d_o);
-          atomicAdd(dst + 6, d_r);
-          atomicAdd(dst + 7, d_g);
-          atomicAdd(dst + 8, d_b);
-        }
+        const float tot = wave_reduce9_transposed(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r,
+                                                  d_g, d_b);
+        if (lane < GS_GRAD2D_FLOATS)
+          atomicAdd(grad2d + (size_t)s_gid[wave][k] * GS_GRAD2D_FLOATS + lane, tot);
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-// L1 loss gradient: one thread per pixel of the concatenated views.
+// L1 loss gradient: a bounded grid per view (blockIdx.y) strides over its pixels;
+// each block adds one partial loss.
 __global__ void __launch_bounds__(256)
 loss_l1_kernel(const float* __restrict__ image, const float* __restrict__ target, TileViews tv,
                float* __restrict__ dL, float* __restrict__ loss) {
-  __shared__ float s_part[4];
-  const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = tv.pix_offset[tv.n_views];
-  // blocks never straddle views: the grid is laid out per view (blockIdx.y = view)
+  __shared__ float s_part[256 / kWave];
   const int v = blockIdx.y;
   const int64_t HW = tv.pix_offset[v + 1] - tv.pix_offset[v];
+  const int64_t base = 3 * tv.pix_offset[v];
+  const float inv = 1.0f / (3.0f * (float)HW);
   float part = 0.0f;
-  if (pix < HW) {
-    const float inv = 1.0f / (3.0f * (float)HW);
-    const int64_t base = 3 * tv.pix_offset[v];
+  for (int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x; pix < HW;
+       pix += (int64_t)gridDim.x * 256) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t k = base + c * HW + pix;
@@ -298,7 +300,6 @@ loss_l1_kernel(const float* __restrict__ image, const float* __restrict__ target
       part += fabsf(d) * inv;
     }
   }
-  (void)total;
   if (loss) {
     part = wave_sum_to_lane63(part);
     if (__lane_id() == kWave - 1) s_part[threadIdx.x / kWave] = part;
@@ -363,7 +364,8 @@ extern "C" int gs_loss_l1(const float* image, const float* target, const gs_came
   for (int v = 0; v < n_views; ++v)
     max_hw = std::max<int64_t>(max_hw, tv.pix_offset[v + 1] - tv.pix_offset[v]);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  loss_l1_kernel<<<dim3((unsigned)((max_hw + 255) / 256), (unsigned)n_views), 256, 0, s>>>(
+  const unsigned bx = (unsigned)std::min<int64_t>((max_hw + 255) / 256, 256);
+  loss_l1_kernel<<<dim3(bx, (unsigned)n_views), 256, 0, s>>>(
       image, target, tv, dL_dimage, loss);
   return launch_status();
 }
