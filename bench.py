@@ -23,8 +23,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # FP32 vector issue rate without packed-FP32 instructions: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s; an FMA counts as two flops.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def parse():
@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -133,6 +136,15 @@ def main():
         per_view = V * args.steps / (b - a)
         log(f"[bench] per-view: {per_view:.1f} views/s")
 
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+
     roof = roofline(stages, state, count, sc.n, V)
     cpu = None if args.no_cpu_baseline else cpu_baseline(log)
 
@@ -227,54 +239,99 @@ def time_stages(rast, params, cams, target, steps, zero_loss):
     return {"ms": {k: v / steps for k, v in acc.items()}, "state": st_last}
 
 
-def roofline(stages, state, count, n, V):
-    """Roofline of the dominant kernel: the blend backward (VALU bound), with its
-    algorithmic work counted from the forward state."""
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2308_04079_amd", "csrc", "gs_render.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "render_traffic_full1080x4.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256_16") != kernel_source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["hbm_bytes_per_launch"]
+
+
+def processed_pairs(st, T=16):
+    """(wave, Gaussian) pairs the blend-backward launch evaluates, counted exactly.
+
+    A wave owns an 8x8 pixel block of a tile; it walks the tile's list from the
+    block's last contributor back to the start and evaluates (on all 64 lanes)
+    every entry whose 3-sigma pixel box meets its block.
+    """
     import torch
+    dev = st.ranges.device
+    M = int(st.count.item())
+    vals = st.vals[:M].long() & 0xFFFFFFFF
+    tile = (st.keys[:M] >> 32).long()
+    rec = st.record.view(-1, 12)
+    lo = rec[vals, 0].view(torch.int32).long()
+    hi = rec[vals, 1].view(torch.int32).long()
+    ilo, jlo, ihi, jhi = lo & 0xFFFF, (lo >> 16) & 0xFFFF, hi & 0xFFFF, (hi >> 16) & 0xFFFF
+    pos = torch.arange(M, device=dev)
+    toff = torch.tensor(st.tile_offset, device=dev)
+    view = torch.searchsorted(toff, tile, right=True) - 1
+    total = 0
+    for v in range(st.n_views):
+        cam = st.cams[v]
+        W, H = cam.width, cam.height
+        tx_n, ty_n = (W + T - 1) // T, (H + T - 1) // T
+        last = st.view_plane(st.last_idx, v).long()
+        # per 8x8 block: the largest last index (-1 if none)
+        Hp, Wp = ty_n * T, tx_n * T
+        pad = torch.full((Hp, Wp), -1, dtype=torch.long, device=dev)
+        pad[:H, :W] = last
+        blk = pad.view(Hp // 8, 8, Wp // 8, 8).amax(dim=(1, 3))          # (Hp/8, Wp/8)
+        sel = view == v
+        t_local = tile[sel] - st.tile_offset[v]
+        tyi, txi = t_local // tx_n, t_local % tx_n
+        for qy in range(T // 8):
+            for qx in range(T // 8):
+                by, bx = tyi * (T // 8) + qy, txi * (T // 8) + qx
+                x0, y0 = bx * 8, by * 8
+                inside = (x0 < W) & (y0 < H)
+                x1, y1 = torch.clamp(x0 + 7, max=W - 1), torch.clamp(y0 + 7, max=H - 1)
+                ov = (ilo[sel] <= x1) & (ihi[sel] >= x0) & (jlo[sel] <= y1) & (jhi[sel] >= y0)
+                wl = blk[by.clamp(max=blk.shape[0] - 1), bx.clamp(max=blk.shape[1] - 1)]
+                total += int((inside & ov & (pos[sel] <= wl)).sum().item())
+    return total
+
+
+def roofline(stages, state, count, n, V):
+    """Roofline of the dominant kernel. For the blend kernels (VALU bound): lane
+    evaluations actually issued (processed pairs x 64) x the arithmetic of one
+    evaluation, against the FP32 VALU issue rate."""
     ms = stages["ms"]
     dom = max(("render_fwd", "render_bwd", "project", "project_bwd", "sort"), key=lambda k: ms[k])
     st = stages["state"]
-    # E' = sum over pixels of the list entries at or before the pixel's last contributor
-    ranges = st.ranges.view(-1, 2).long()
-    evals = 0
-    for v in range(st.n_views):
-        cam = st.cams[v]
-        T = 16
-        tx = (cam.width + T - 1) // T
-        last = st.view_plane(st.last_idx, v).long()
-        ys = torch.arange(cam.height, device=last.device) // T
-        xs = torch.arange(cam.width, device=last.device) // T
-        tile = st.tile_offset[v] + ys[:, None] * tx + xs[None, :]
-        start = ranges[tile, 0]
-        evals += int(torch.clamp(last - start + 1, min=0).sum().item())
-    if dom == "render_bwd":
-        flops_per_eval = BWD_FLOPS_PER_EVAL
-    elif dom == "render_fwd":
-        flops_per_eval = FWD_FLOPS_PER_EVAL
-    else:
-        flops_per_eval = None
-    if flops_per_eval is not None:
-        achieved = evals * flops_per_eval / (ms[dom] * 1e-3) / 1e12
+    if dom in ("render_bwd", "render_fwd"):
+        pairs = processed_pairs(st)
+        ops = BWD_OPS_PER_EVAL if dom == "render_bwd" else FWD_OPS_PER_EVAL
+        lane_evals = pairs * 64
+        achieved = lane_evals * ops / (ms[dom] * 1e-3) / 1e12
         return {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
-                "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
-                "units": {"evaluations": evals, "flops_per_evaluation": flops_per_eval}}
-    # HBM-bound stages: algorithmic bytes
+                "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s (FP32 VALU lane-ops)",
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(dom),
+                "units": {"wave_gaussian_pairs": pairs, "lane_evaluations": lane_evals,
+                          "ops_per_evaluation": ops}}
     K = 16
-    per = {"project": (4 * (11 + 3 * K) + 56 * V), "project_bwd": (4 * (11 + 3 * K) * 2 + 36 * V)}
+    per = {"project": (4 * (11 + 3 * K) + 56 * V), "project_bwd": (4 * (11 + 3 * K) * 2 + 40 * V)}
     b = per.get(dom, 24) * (n if dom in per else count)
     achieved = b / (ms[dom] * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
 
 
-# Algorithmic FP32 flops of one (pixel, Gaussian) evaluation as the method states
-# it (FMA = 2): forward = offset (4) + Mahalanobis distance (8) + exp argument and
-# exp (2) + alpha (2) + three threshold tests (3) + T' (2) + colour (7) = 28;
-# backward adds the T recovery (2), colour and alpha gradients (15), the
-# opacity/mean/conic gradients (14) and the back-to-front accumulator (6) = 65.
-FWD_FLOPS_PER_EVAL = 28
-BWD_FLOPS_PER_EVAL = 65
+# FP32 VALU operations of one (pixel, Gaussian) evaluation as the method states it
+# (one op per add, mul, fma, compare, select, min, exp, reciprocal): the forward
+# evaluation is 22 ops, the backward one 48 (see DESIGN.md for the itemisation).
+FWD_OPS_PER_EVAL = 22
+BWD_OPS_PER_EVAL = 48
 
 
 def cpu_baseline(log):

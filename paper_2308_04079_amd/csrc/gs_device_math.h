@@ -21,73 +21,88 @@ constexpr double kY3c = 0.4570457994644658;   // sqrt(21 / (32 pi))
 constexpr double kY3d = 0.3731763325901154;   // sqrt(7 / (16 pi))
 constexpr double kY3e = 1.445305721320277;    // sqrt(105 / (16 pi))
 
+// FP32 evaluation (the colour's error, ~1e-7, is far below the image tolerance):
+// Y[k] for the unit direction (x, y, z).
 template <int DEG>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
-  Y[0] = kY0;
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  Y[0] = (float)kY0;
   if constexpr (DEG >= 1) {
-    Y[1] = kY1 * y;
-    Y[2] = kY1 * z;
-    Y[3] = kY1 * x;
+    Y[1] = (float)kY1 * y;
+    Y[2] = (float)kY1 * z;
+    Y[3] = (float)kY1 * x;
   }
   if constexpr (DEG >= 2) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kY2a * x * y;
-    Y[5] = kY2a * y * z;
-    Y[6] = kY2b * (3.0 * zz - 1.0);
-    Y[7] = kY2a * x * z;
-    Y[8] = kY2c * (xx - yy);
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = (float)kY2a * x * y;
+    Y[5] = (float)kY2a * y * z;
+    Y[6] = (float)kY2b * (3.0f * zz - 1.0f);
+    Y[7] = (float)kY2a * x * z;
+    Y[8] = (float)kY2c * (xx - yy);
     if constexpr (DEG >= 3) {
-      Y[9] = kY3a * y * (3.0 * xx - yy);
-      Y[10] = kY3b * x * y * z;
-      Y[11] = kY3c * y * (5.0 * zz - 1.0);
-      Y[12] = kY3d * z * (5.0 * zz - 3.0);
-      Y[13] = kY3c * x * (5.0 * zz - 1.0);
-      Y[14] = kY3e * z * (xx - yy);
-      Y[15] = kY3a * x * (xx - 3.0 * yy);
+      Y[9] = (float)kY3a * y * (3.0f * xx - yy);
+      Y[10] = (float)kY3b * x * y * z;
+      Y[11] = (float)kY3c * y * (5.0f * zz - 1.0f);
+      Y[12] = (float)kY3d * z * (5.0f * zz - 3.0f);
+      Y[13] = (float)kY3c * x * (5.0f * zz - 1.0f);
+      Y[14] = (float)kY3e * z * (xx - yy);
+      Y[15] = (float)kY3a * x * (xx - 3.0f * yy);
     }
   }
 }
 
-// Gradient of each basis polynomial with respect to (x, y, z): G[k][0..2].
+// g = sum_k w[k] grad Y_k(x, y, z): the gradient of each basis polynomial with
+// respect to (x, y, z), weighted and summed without storing it.
 template <int DEG>
-__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, double (*G)[3]) {
-  G[0][0] = G[0][1] = G[0][2] = 0.0;
+__device__ __forceinline__ void sh_weighted_grad(float x, float y, float z, const float* w, float* g) {
+  g[0] = g[1] = g[2] = 0.0f;
   if constexpr (DEG >= 1) {
-    G[1][0] = 0.0;  G[1][1] = kY1;  G[1][2] = 0.0;
-    G[2][0] = 0.0;  G[2][1] = 0.0;  G[2][2] = kY1;
-    G[3][0] = kY1;  G[3][1] = 0.0;  G[3][2] = 0.0;
+    g[0] += (float)kY1 * w[3];
+    g[1] += (float)kY1 * w[1];
+    g[2] += (float)kY1 * w[2];
   }
   if constexpr (DEG >= 2) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    G[4][0] = kY2a * y;        G[4][1] = kY2a * x;         G[4][2] = 0.0;
-    G[5][0] = 0.0;             G[5][1] = kY2a * z;         G[5][2] = kY2a * y;
-    G[6][0] = 0.0;             G[6][1] = 0.0;              G[6][2] = kY2b * 6.0 * z;
-    G[7][0] = kY2a * z;        G[7][1] = 0.0;              G[7][2] = kY2a * x;
-    G[8][0] = kY2c * 2.0 * x;  G[8][1] = -kY2c * 2.0 * y;  G[8][2] = 0.0;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float a = (float)kY2a, b = (float)kY2b, c = (float)kY2c;
+    g[0] += a * (y * w[4] + z * w[7]) + c * 2.0f * x * w[8];
+    g[1] += a * (x * w[4] + z * w[5]) - c * 2.0f * y * w[8];
+    g[2] += a * (y * w[5] + x * w[7]) + b * 6.0f * z * w[6];
     if constexpr (DEG >= 3) {
-      G[9][0] = kY3a * 6.0 * x * y;
-      G[9][1] = kY3a * (3.0 * xx - 3.0 * yy);
-      G[9][2] = 0.0;
-      G[10][0] = kY3b * y * z;
-      G[10][1] = kY3b * x * z;
-      G[10][2] = kY3b * x * y;
-      G[11][0] = 0.0;
-      G[11][1] = kY3c * (5.0 * zz - 1.0);
-      G[11][2] = kY3c * 10.0 * y * z;
-      G[12][0] = 0.0;
-      G[12][1] = 0.0;
-      G[12][2] = kY3d * (15.0 * zz - 3.0);
-      G[13][0] = kY3c * (5.0 * zz - 1.0);
-      G[13][1] = 0.0;
-      G[13][2] = kY3c * 10.0 * x * z;
-      G[14][0] = kY3e * 2.0 * x * z;
-      G[14][1] = -kY3e * 2.0 * y * z;
-      G[14][2] = kY3e * (xx - yy);
-      G[15][0] = kY3a * (3.0 * xx - 3.0 * yy);
-      G[15][1] = -kY3a * 6.0 * x * y;
-      G[15][2] = 0.0;
+      const float A = (float)kY3a, B = (float)kY3b, C = (float)kY3c, D = (float)kY3d,
+                  E = (float)kY3e;
+      g[0] += A * 6.0f * x * y * w[9] + B * y * z * w[10] + C * (5.0f * zz - 1.0f) * w[13] +
+              E * 2.0f * x * z * w[14] + A * (3.0f * xx - 3.0f * yy) * w[15];
+      g[1] += A * (3.0f * xx - 3.0f * yy) * w[9] + B * x * z * w[10] +
+              C * (5.0f * zz - 1.0f) * w[11] - E * 2.0f * y * z * w[14] - A * 6.0f * x * y * w[15];
+      g[2] += B * x * y * w[10] + C * 10.0f * y * z * w[11] + D * (15.0f * zz - 3.0f) * w[12] +
+              C * 10.0f * x * z * w[13] + E * (xx - yy) * w[14];
     }
   }
+}
+
+// Unit view direction from the camera centre to the mean (FP64 difference, FP32 result).
+__device__ __forceinline__ float view_dir(const float* Rw, const float* tw, double x, double y,
+                                          double z, float* d) {
+  double cc[3];
+  for (int k = 0; k < 3; ++k)
+    cc[k] = -((double)Rw[0 * 3 + k] * tw[0] + (double)Rw[1 * 3 + k] * tw[1] +
+              (double)Rw[2 * 3 + k] * tw[2]);
+  const double ex = x - cc[0], ey = y - cc[1], ez = z - cc[2];
+  const double dist = sqrt(ex * ex + ey * ey + ez * ez);
+  const double idist = 1.0 / dist;
+  d[0] = (float)(ex * idist);
+  d[1] = (float)(ey * idist);
+  d[2] = (float)(ez * idist);
+  return (float)dist;
+}
+
+// Colour before the clamp, per channel: sum_k sh[k][ch] Y[k] + 0.5, in a fixed
+// order so the forward and backward passes take the same clamp decision.
+template <int K>
+__device__ __forceinline__ float sh_colour_raw(const float (*shc)[3], const float* Y, int ch) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc = fmaf(shc[k][ch], Y[k], acc);
+  return acc + 0.5f;
 }
 
 // Rotation of a unit quaternion (r, i, j, k): App. A, Eq. (quat).
@@ -113,7 +128,7 @@ __device__ __forceinline__ double cam_row(const float* Rrow, float t, double x, 
 
 // Everything the forward and backward projection derive from one (Gaussian, view).
 struct ProjGeom {
-  double tx, ty, tz;        // camera-space mean
+  double tx, ty, tz, iz;    // camera-space mean and 1 / tz
   double WM[9];             // W * M, row-major
   double A0[3], A1[3];      // rows of A = J W M (Sigma' = A A^T)
   double a, b, c, det;      // Sigma' = [[a, b], [b, c]], det by Cauchy-Binet
@@ -130,23 +145,25 @@ __device__ __forceinline__ double floor_clamped(double x, double lo, double hi) 
   return fmin(fmax(floor(x), lo), hi);
 }
 
-__device__ __forceinline__ void project_geometry(const Cam& cam, const Rules& rules, double x,
-                                                 double y, double z, const double* M,
-                                                 ProjGeom& p) {
+// Camera transform, near cull and the 2D covariance Sigma' = A A^T with A = J W M
+// (Sec. 4, Eq. volume-render; J the pinhole Jacobian at the camera-space mean).
+// Shared by both passes; returns false when the Gaussian is culled here.
+__device__ __forceinline__ bool project_covariance(const Cam& cam, const Rules& rules, double x,
+                                                   double y, double z, const double* M,
+                                                   ProjGeom& p) {
   p.tx = cam_row(cam.R + 0, cam.t[0], x, y, z);
   p.ty = cam_row(cam.R + 3, cam.t[1], x, y, z);
   p.tz = cam_row(cam.R + 6, cam.t[2], x, y, z);
-  p.ok = ((float)p.tz >= rules.near_z);  // near cull on the FP32 depth
-  if (!p.ok) return;
+  if (!((float)p.tz >= rules.near_z)) return false;  // near cull on the FP32 depth
   for (int r = 0; r < 3; ++r)
     for (int c2 = 0; c2 < 3; ++c2)
       p.WM[r * 3 + c2] = (double)cam.R[r * 3 + 0] * M[0 * 3 + c2] +
                          (double)cam.R[r * 3 + 1] * M[1 * 3 + c2] +
                          (double)cam.R[r * 3 + 2] * M[2 * 3 + c2];
   const double fx = cam.fx, fy = cam.fy;
-  const double iz = 1.0 / p.tz;
-  const double J00 = fx * iz, J02 = -fx * p.tx * iz * iz;
-  const double J11 = fy * iz, J12 = -fy * p.ty * iz * iz;
+  p.iz = 1.0 / p.tz;
+  const double J00 = fx * p.iz, J02 = -fx * p.tx * p.iz * p.iz;
+  const double J11 = fy * p.iz, J12 = -fy * p.ty * p.iz * p.iz;
   for (int c2 = 0; c2 < 3; ++c2) {
     p.A0[c2] = J00 * p.WM[0 * 3 + c2] + J02 * p.WM[2 * 3 + c2];
     p.A1[c2] = J11 * p.WM[1 * 3 + c2] + J12 * p.WM[2 * 3 + c2];
@@ -159,10 +176,18 @@ __device__ __forceinline__ void project_geometry(const Cam& cam, const Rules& ru
   const double m02 = p.A0[0] * p.A1[2] - p.A0[2] * p.A1[0];
   const double m12 = p.A0[1] * p.A1[2] - p.A0[2] * p.A1[1];
   p.det = m01 * m01 + m02 * m02 + m12 * m12;
-  p.u = fx * p.tx / p.tz + (double)cam.cx;
-  p.v = fy * p.ty / p.tz + (double)cam.cy;
-  p.ok = (p.det > 0.0) && isfinite(p.det) && isfinite(p.a) && isfinite(p.c) &&
-         isfinite(p.u) && isfinite(p.v);
+  return (p.det > 0.0) && isfinite(p.det) && isfinite(p.a) && isfinite(p.c);
+}
+
+// Projected mean and 3-sigma pixel box (forward only).
+__device__ __forceinline__ void project_geometry(const Cam& cam, const Rules& rules, double x,
+                                                 double y, double z, const double* M,
+                                                 ProjGeom& p) {
+  p.ok = project_covariance(cam, rules, x, y, z, M, p);
+  if (!p.ok) return;
+  p.u = (double)cam.fx * p.tx * p.iz + (double)cam.cx;
+  p.v = (double)cam.fy * p.ty * p.iz + (double)cam.cy;
+  p.ok = isfinite(p.u) && isfinite(p.v);
   if (!p.ok) return;
   const double ext = (double)rules.ext;
   const double rx = ext * sqrt(p.a), ry = ext * sqrt(p.c);

@@ -9,6 +9,15 @@ namespace gs {
 
 constexpr int kProjBlock = 256;
 
+template <int K>
+__device__ __forceinline__ void load_sh(const float* __restrict__ sh, int64_t n, int64_t g,
+                                        float (*shc)[3]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) shc[k][ch] = sh[((int64_t)k * 3 + ch) * n + g];
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(kProjBlock)
 project_kernel(const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -23,24 +32,21 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
   const float ls0 = log_scales[g], ls1 = log_scales[n + g], ls2 = log_scales[2 * n + g];
   const float q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
   const float lg = logits[g];
-  float shc[K][3];
   bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ls0) && isfinite(ls1) &&
                 isfinite(ls2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) &&
                 isfinite(lg);
+  float shc[K][3];
+  load_sh<K>(sh, n, g, shc);
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      shc[k][ch] = sh[((int64_t)k * 3 + ch) * n + g];
-      finite = finite && isfinite(shc[k][ch]);
-    }
+  for (int k = 0; k < K; ++k) finite = finite && isfinite(shc[k][0] + shc[k][1] + shc[k][2]);
   const double qn = sqrt((double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3);
   const bool alive = finite && qn > 0.0;
   double M[9];
   double opac = 0.0;
   if (alive) {
     double R[9];
-    quat_to_rot(q0 / qn, q1 / qn, q2 / qn, q3 / qn, R);
+    const double iq = 1.0 / qn;
+    quat_to_rot(q0 * iq, q1 * iq, q2 * iq, q3 * iq, R);
     const double s0 = exp((double)ls0), s1 = exp((double)ls1), s2 = exp((double)ls2);
     for (int r = 0; r < 3; ++r) {
       M[r * 3 + 0] = R[r * 3 + 0] * s0;
@@ -58,46 +64,34 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
       project_geometry(cam, rules, x, y, z, M, p);
       ok = p.ok;
     }
-    double rgb[3] = {0.0, 0.0, 0.0};
-    if (ok) {
-      // view direction: from the camera centre -R^T t to the mean
-      const double ccx = -((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1] + (double)cam.R[6] * cam.t[2]);
-      const double ccy = -((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1] + (double)cam.R[7] * cam.t[2]);
-      const double ccz = -((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1] + (double)cam.R[8] * cam.t[2]);
-      const double dx = x - ccx, dy = y - ccy, dz = z - ccz;
-      const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-      ok = dist > 0.0;
-      double Y[K];
-      sh_basis<DEG>(dx / dist, dy / dist, dz / dist, Y);
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc += (double)shc[k][ch] * Y[k];
-        rgb[ch] = fmax(acc + 0.5, 0.0);
-      }
-    }
+    float d[3];
+    if (ok) ok = view_dir(cam.R, cam.t, x, y, z, d) > 0.0f;
     if (!ok) {
       tiles_touched[idx] = 0;
       continue;
     }
+    float Y[K];
+    sh_basis<DEG>(d[0], d[1], d[2], Y);
+    const float r = fmaxf(sh_colour_raw<K>(shc, Y, 0), 0.0f);
+    const float gc = fmaxf(sh_colour_raw<K>(shc, Y, 1), 0.0f);
+    const float b = fmaxf(sh_colour_raw<K>(shc, Y, 2), 0.0f);
     const int T = views.tile;
-    const int ntx = p.i_hi / T - p.i_lo / T + 1;
-    const int nty = p.j_hi / T - p.j_lo / T + 1;
-    tiles_touched[idx] = ntx * nty;
+    tiles_touched[idx] = (p.i_hi / T - p.i_lo / T + 1) * (p.j_hi / T - p.j_lo / T + 1);
     const float z32 = (float)p.tz;
     depth_key[idx] = __float_as_uint(z32);
-    const double sa = sqrt(p.a), sd = sqrt(p.det);
+    // whitening L^-1 of Sigma' = L L^T: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
+    const double sa = sqrt(p.a), isa = 1.0 / sa, isd = 1.0 / sqrt(p.det);
     float4* rec = reinterpret_cast<float4*>(record + idx * GS_RECORD_FLOATS);
     rec[0] = make_float4(__int_as_float(p.i_lo | (p.j_lo << 16)), __int_as_float(p.i_hi | (p.j_hi << 16)),
                          (float)(p.u - p.i_lo), (float)(p.v - p.j_lo));
-    rec[1] = make_float4((float)(1.0 / sa), (float)(-p.b / (sa * sd)), (float)(sa / sd), (float)opac);
-    rec[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], z32);
+    rec[1] = make_float4((float)isa, (float)(-p.b * isa * isd), (float)(sa * isd), (float)opac);
+    rec[2] = make_float4(r, gc, b, z32);
   }
 }
 
 // ---------------------------------------------------------------------------
-// backward
+// backward: one loop over the views for the geometry (FP64) and one for the SH
+// colour (FP32), so their registers are not live at the same time
 // ---------------------------------------------------------------------------
 
 template <int DEG>
@@ -112,19 +106,17 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   if (g >= n) return;
-  double dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dqh[4] = {0, 0, 0, 0}, dop = 0.0;
-  double dshc[K][3];
-#pragma unroll
-  for (int k = 0; k < K; ++k) dshc[k][0] = dshc[k][1] = dshc[k][2] = 0.0;
-
   bool any = false;
   for (int v = 0; v < views.n_views; ++v) any = any || tiles_touched[(int64_t)v * n + g] > 0;
-  double qn = 0.0, qh[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0}, opac = 0.0;
+  const double x = means[g], y = means[n + g], z = means[2 * n + g];
+  float dmu_f[3] = {0.0f, 0.0f, 0.0f};
+  {
+  double dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0};
+  double dop = 0.0, opac = 0.0;
   if (any) {
-    const double x = means[g], y = means[n + g], z = means[2 * n + g];
     const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
-    qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    qh[0] = q0 / qn; qh[1] = q1 / qn; qh[2] = q2 / qn; qh[3] = q3 / qn;
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3), iq = 1.0 / qn;
+    const double qh[4] = {q0 * iq, q1 * iq, q2 * iq, q3 * iq};
     double R[9], M[9];
     quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
     s[0] = exp((double)log_scales[g]);
@@ -133,39 +125,33 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * s[c];
     opac = 1.0 / (1.0 + exp(-(double)logits[g]));
-    float shc[K][3];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) shc[k][ch] = sh[((int64_t)k * 3 + ch) * n + g];
-
     double dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int v = 0; v < views.n_views; ++v) {
       const int64_t idx = (int64_t)v * n + g;
       if (tiles_touched[idx] <= 0) continue;
       const Cam& cam = views.cam[v];
       ProjGeom p;
-      project_geometry(cam, rules, x, y, z, M, p);
+      project_covariance(cam, rules, x, y, z, M, p);
       const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
       const double du = gr[0], dv = gr[1], dw00 = gr[2], dw10 = gr[3], dw11 = gr[4];
       dop += gr[5];
       // whitening W = L^-1: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
-      const double a = p.a, b = p.b, c = p.c, det = p.det;
-      const double sa = sqrt(a), sd = sqrt(det);
-      const double isasd = 1.0 / (sa * sd), idet = 1.0 / det;
-      const double gA = dw00 * (-0.5 / (a * sa)) +
-                        dw10 * (0.5 * b / a * isasd + 0.5 * b * c * isasd * idet) +
-                        dw11 * (0.5 * isasd - 0.5 * sa * c * idet / sd);
-      const double gB = dw10 * (-isasd - b * b * isasd * idet) + dw11 * (sa * b * idet / sd);
-      const double gC = dw10 * (0.5 * b * sa * idet / sd) + dw11 * (-0.5 * a * sa * idet / sd);
+      const double a = p.a, b = p.b, c = p.c;
+      const double sa = sqrt(a), isa = 1.0 / sa, isd = 1.0 / sqrt(p.det);
+      const double isasd = isa * isd, idet = isd * isd, ia = isa * isa;
+      const double gA = dw00 * (-0.5 * ia * isa) +
+                        dw10 * (0.5 * b * ia * isasd + 0.5 * b * c * isasd * idet) +
+                        dw11 * (0.5 * isasd - 0.5 * sa * c * idet * isd);
+      const double gB = dw10 * (-isasd - b * b * isasd * idet) + dw11 * (sa * b * idet * isd);
+      const double gC = dw10 * (0.5 * b * sa * idet * isd) + dw11 * (-0.5 * a * sa * idet * isd);
       // Sigma' = A A^T: dA0 = 2 gA A0 + gB A1, dA1 = gB A0 + 2 gC A1
       double dA0[3], dA1[3];
       for (int k = 0; k < 3; ++k) {
         dA0[k] = 2.0 * gA * p.A0[k] + gB * p.A1[k];
         dA1[k] = gB * p.A0[k] + 2.0 * gC * p.A1[k];
       }
-      const double fx = cam.fx, fy = cam.fy, tx = p.tx, ty = p.ty, tz = p.tz;
-      const double iz = 1.0 / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+      const double fx = cam.fx, fy = cam.fy, tx = p.tx, ty = p.ty;
+      const double iz = p.iz, iz2 = iz * iz, iz3 = iz2 * iz;
       const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
       double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0, dWM[9];
       for (int k = 0; k < 3; ++k) {
@@ -192,42 +178,6 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
       for (int k = 0; k < 3; ++k)
         dmu[k] += (double)cam.R[0 * 3 + k] * dtx + (double)cam.R[1 * 3 + k] * dty +
                   (double)cam.R[2 * 3 + k] * dtz;
-      // colour: SH coefficients and the view direction
-      const double ccx = -((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1] + (double)cam.R[6] * cam.t[2]);
-      const double ccy = -((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1] + (double)cam.R[7] * cam.t[2]);
-      const double ccz = -((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1] + (double)cam.R[8] * cam.t[2]);
-      const double ex = x - ccx, ey = y - ccy, ez = z - ccz;
-      const double dist = sqrt(ex * ex + ey * ey + ez * ez);
-      const double dx = ex / dist, dy = ey / dist, dz = ez / dist;
-      double Y[K];
-      sh_basis<DEG>(dx, dy, dz, Y);
-      double dcol[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc += (double)shc[k][ch] * Y[k];
-        dcol[ch] = (acc + 0.5 >= 0.0) ? (double)gr[6 + ch] : 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) dshc[k][ch] += Y[k] * dcol[ch];
-      }
-      if constexpr (DEG > 0) {
-        double G[K][3];
-        sh_basis_grad<DEG>(dx, dy, dz, G);
-        double ddir[3] = {0, 0, 0};
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-          const double w = (double)shc[k][0] * dcol[0] + (double)shc[k][1] * dcol[1] +
-                           (double)shc[k][2] * dcol[2];
-          ddir[0] += w * G[k][0];
-          ddir[1] += w * G[k][1];
-          ddir[2] += w * G[k][2];
-        }
-        const double radial = dx * ddir[0] + dy * ddir[1] + dz * ddir[2];
-        dmu[0] += (ddir[0] - dx * radial) / dist;
-        dmu[1] += (ddir[1] - dy * radial) / dist;
-        dmu[2] += (ddir[2] - dz * radial) / dist;
-      }
     }
     // M = R diag(s): dR_ij = dM_ij s_j, ds_j = sum_i dM_ij R_ij
     double dR[9];
@@ -236,8 +186,9 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
         dR[i * 3 + j] = dM[i * 3 + j] * s[j];
         ds[j] += dM[i * 3 + j] * R[i * 3 + j];
       }
-    // derivative of Eq. (quat) with respect to (r, i, j, k)
+    // derivative of Eq. (quat) with respect to (r, i, j, k), then the normalisation
     const double r = qh[0], i = qh[1], j = qh[2], k = qh[3];
+    double dqh[4];
     dqh[0] = 2.0 * (-k * dR[1] + j * dR[2] + k * dR[3] - i * dR[5] - j * dR[6] + i * dR[7]);
     dqh[1] = 2.0 * (j * dR[1] + k * dR[2] + j * dR[3] - 2.0 * i * dR[4] - r * dR[5] + k * dR[6] +
                     r * dR[7] - 2.0 * i * dR[8]);
@@ -245,25 +196,67 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
                     k * dR[7] - 2.0 * j * dR[8]);
     dqh[3] = 2.0 * (-2.0 * k * dR[0] - r * dR[1] + i * dR[2] + r * dR[3] - 2.0 * k * dR[4] +
                     j * dR[5] + i * dR[6] + j * dR[7]);
-  }
-  // quaternion normalisation and activations
-  double dq[4] = {0, 0, 0, 0};
-  if (any) {
     const double dotq = qh[0] * dqh[0] + qh[1] * dqh[1] + qh[2] * dqh[2] + qh[3] * dqh[3];
-    for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - qh[c] * dotq) / qn;
+    for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - qh[c] * dotq) * iq;
   }
-  d_means[g] = (float)dmu[0];
-  d_means[n + g] = (float)dmu[1];
-  d_means[2 * n + g] = (float)dmu[2];
+  // the geometry gradients are final here; only the mean still gains the SH term
   d_log_scales[g] = (float)(ds[0] * s[0]);
   d_log_scales[n + g] = (float)(ds[1] * s[1]);
   d_log_scales[2 * n + g] = (float)(ds[2] * s[2]);
   for (int c = 0; c < 4; ++c) d_quats[(int64_t)c * n + g] = (float)dq[c];
   d_logits[g] = (float)(dop * opac * (1.0 - opac));
+  dmu_f[0] = (float)dmu[0];
+  dmu_f[1] = (float)dmu[1];
+  dmu_f[2] = (float)dmu[2];
+  }
+  // SH colour: coefficient gradients and the view-direction term of the mean. The
+  // barrier keeps the coefficient loads from being hoisted into the geometry loop.
+  asm volatile("" ::: "memory");
+  float dshc[K][3];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) dshc[kk][0] = dshc[kk][1] = dshc[kk][2] = 0.0f;
+  if (any) {
+    float shc[K][3];
+    load_sh<K>(sh, n, g, shc);
+    for (int v = 0; v < views.n_views; ++v) {
+      const int64_t idx = (int64_t)v * n + g;
+      if (tiles_touched[idx] <= 0) continue;
+      const Cam& cam = views.cam[v];
+      float d[3];
+      const float dist = view_dir(cam.R, cam.t, x, y, z, d);
+      float Y[K];
+      sh_basis<DEG>(d[0], d[1], d[2], Y);
+      const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
+      float dcol[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        // the forward clamped the colour at 0: no gradient through a clamped channel
+        dcol[ch] = (sh_colour_raw<K>(shc, Y, ch) >= 0.0f) ? gr[6 + ch] : 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) dshc[kk][ch] = fmaf(Y[kk], dcol[ch], dshc[kk][ch]);
+      }
+      if constexpr (DEG > 0) {
+        float w[K], ddir[3];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+          w[kk] = shc[kk][0] * dcol[0] + shc[kk][1] * dcol[1] + shc[kk][2] * dcol[2];
+        sh_weighted_grad<DEG>(d[0], d[1], d[2], w, ddir);
+        // d = e / |e|: dL/de = (I - d d^T) dL/dd / |e|
+        const float radial = d[0] * ddir[0] + d[1] * ddir[1] + d[2] * ddir[2];
+        const float idist = 1.0f / dist;
+        dmu_f[0] += (ddir[0] - d[0] * radial) * idist;
+        dmu_f[1] += (ddir[1] - d[1] * radial) * idist;
+        dmu_f[2] += (ddir[2] - d[2] * radial) * idist;
+      }
+    }
+  }
+  d_means[g] = dmu_f[0];
+  d_means[n + g] = dmu_f[1];
+  d_means[2 * n + g] = dmu_f[2];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk)
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) d_sh[((int64_t)kk * 3 + ch) * n + g] = (float)dshc[kk][ch];
+    for (int ch = 0; ch < 3; ++ch) d_sh[((int64_t)kk * 3 + ch) * n + g] = dshc[kk][ch];
 }
 
 }  // namespace gs
