@@ -99,8 +99,9 @@ def main():
     for _ in range(args.warmup):
         state, grads, loss = step(rast, cams, target)
     torch.cuda.synchronize()
-    st, count = state.read_status()
-    assert st == 0, f"device status {st} after warm-up"
+    if args.warmup > 0:
+        st, count = state.read_status()
+        assert st == 0, f"device status {st} after warm-up"
     log(f"[bench] warm-up done: M={count} instances for {V} views")
 
     torch.cuda.synchronize()
@@ -209,15 +210,16 @@ def time_stages(rast, params, cams, target, steps, zero_loss):
                                        ctypes.byref(inst), _lib.ptr(bin_ws), bin_ws.numel(),
                                        stream)),
             ("sort", lambda: lib.gs_sort(ctypes.byref(inst), st.n_tiles, cfg, _lib.ptr(st.ranges),
-                                         _lib.ptr(sort_ws), sort_ws.numel(), stream)),
+                                         _lib.ptr(st.order), _lib.ptr(sort_ws), sort_ws.numel(),
+                                         stream)),
             ("render_fwd", lambda: lib.gs_render_fwd(
-                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), st.cams_c, V, cfg,
-                _lib.ptr(st.image), _lib.ptr(st.T_final), _lib.ptr(st.last_idx), n, stream)),
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), _lib.ptr(st.order),
+                st.cams_c, V, cfg, _lib.ptr(st.image), _lib.ptr(st.T_final), _lib.ptr(st.last_idx), n, stream)),
             ("loss", lambda: lib.gs_loss_l1(_lib.ptr(st.image), _lib.ptr(target), st.cams_c, V,
                                             _lib.ptr(dL), _lib.ptr(loss), stream)),
             ("render_bwd", lambda: lib.gs_render_bwd(
-                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), st.cams_c, V, cfg,
-                _lib.ptr(st.T_final), _lib.ptr(st.last_idx), _lib.ptr(dL), _lib.ptr(grad2d), n,
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), _lib.ptr(st.order),
+                st.cams_c, V, cfg, _lib.ptr(st.T_final), _lib.ptr(st.last_idx), _lib.ptr(dL), _lib.ptr(grad2d), n,
                 stream)),
             ("project_bwd", lambda: lib.gs_project_bwd(ctypes.byref(pr), st.cams_c, V, cfg,
                                                        ctypes.byref(proj), _lib.ptr(grad2d),
@@ -258,11 +260,13 @@ def measured_traffic(kernel):
 
 
 def processed_pairs(st, T=16):
-    """(wave, Gaussian) pairs the blend-backward launch evaluates, counted exactly.
+    """(wave, Gaussian) pairs the blend-backward launch evaluates.
 
     A wave owns an 8x8 pixel block of a tile; it walks the tile's list from the
     block's last contributor back to the start and evaluates (on all 64 lanes)
-    every entry whose 3-sigma pixel box meets its block.
+    every entry whose 3-sigma pixel box meets its block and whose second whitened
+    coordinate is not beyond 3 sigma at all four block corners (the kernel's two
+    staging tests, replayed here in FP64).
     """
     import torch
     dev = st.ranges.device
@@ -273,6 +277,8 @@ def processed_pairs(st, T=16):
     lo = rec[vals, 0].view(torch.int32).long()
     hi = rec[vals, 1].view(torch.int32).long()
     ilo, jlo, ihi, jhi = lo & 0xFFFF, (lo >> 16) & 0xFFFF, hi & 0xFFFF, (hi >> 16) & 0xFFFF
+    mx, my = rec[vals, 2].double(), rec[vals, 3].double()
+    w10, w11 = rec[vals, 5].double(), rec[vals, 6].double()
     pos = torch.arange(M, device=dev)
     toff = torch.tensor(st.tile_offset, device=dev)
     view = torch.searchsorted(toff, tile, right=True) - 1
@@ -297,6 +303,14 @@ def processed_pairs(st, T=16):
                 inside = (x0 < W) & (y0 < H)
                 x1, y1 = torch.clamp(x0 + 7, max=W - 1), torch.clamp(y0 + 7, max=H - 1)
                 ov = (ilo[sel] <= x1) & (ihi[sel] >= x0) & (jlo[sel] <= y1) & (jhi[sel] >= y0)
+                dxa = (x0 - ilo[sel]) + 0.5 - mx[sel]
+                dxb = (x1 - ilo[sel]) + 0.5 - mx[sel]
+                dya = (y0 - jlo[sel]) + 0.5 - my[sel]
+                dyb = (y1 - jlo[sel]) + 0.5 - my[sel]
+                e = torch.stack([w10[sel] * dxa + w11[sel] * dya, w10[sel] * dxb + w11[sel] * dya,
+                                 w10[sel] * dxa + w11[sel] * dyb, w10[sel] * dxb + w11[sel] * dyb])
+                lim = 3.0 * 1.00001
+                ov &= ~((e.min(0).values > lim) | (e.max(0).values < -lim))
                 wl = blk[by.clamp(max=blk.shape[0] - 1), bx.clamp(max=blk.shape[1] - 1)]
                 total += int((inside & ov & (pos[sel] <= wl)).sum().item())
     return total

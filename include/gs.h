@@ -184,10 +184,12 @@ size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total, const gs
  * the M = min(*count, capacity) instances by key (onesweep: one histogram pass,
  * then one pass per digit with decoupled look-back), then per global tile the
  * range [start, end) of its instances, written to tile_ranges[t][2] (uint32).
- * Ties in (tile, depth) keep Gaussian order. */
+ * Ties in (tile, depth) keep Gaussian order. If tile_order (device, [n_tiles_total])
+ * is not NULL it receives a permutation of the tile ids, longest list first
+ * (bucketed by floor(log2(length))), the issue order for the render calls. */
 int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
-            uint32_t* tile_ranges, void* workspace, size_t workspace_bytes,
-            gs_stream_t stream);
+            uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
+            size_t workspace_bytes, gs_stream_t stream);
 
 /* Forward blend (Alg. 2 BlendInOrder; Eq. front-to-back; App. C rules): for every
  * pixel of every view, front to back over its tile's instances: skip pixels
@@ -198,9 +200,12 @@ int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cf
  *   T_final  [H][W] at T_final + P_v        final transmittance
  *   last_idx [H][W] at last_idx + P_v       instance position of the last
  *                                           blended Gaussian, -1 if none
- * n is N (per view); instance values >= V*N are ignored. */
+ * n is N (per view); instance values >= V*N are ignored. tile_order (device,
+ * nullable) is the order in which tiles are issued (from gs_sort); it changes no
+ * output. */
 int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
-                  const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                  const uint32_t* tile_ranges, const uint32_t* tile_order,
+                  const gs_camera* cams, int32_t n_views,
                   const gs_config* cfg, float* image, float* T_final, int32_t* last_idx,
                   int64_t n, gs_stream_t stream);
 
@@ -211,7 +216,8 @@ int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
  *   d(u, v), d(w00, w10, w11), d(opacity), d(r, g, b).
  * grad2d is zeroed by this call (in-stream) before accumulation. */
 int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
-                  const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                  const uint32_t* tile_ranges, const uint32_t* tile_order,
+                  const gs_camera* cams, int32_t n_views,
                   const gs_config* cfg, const float* T_final, const int32_t* last_idx,
                   const float* dL_dimage, float* grad2d, int64_t n, gs_stream_t stream);
 

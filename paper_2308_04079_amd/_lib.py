@@ -77,13 +77,16 @@ EXPORTS = {
                               ctypes.c_void_p]),
     "gs_sort_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64, P(GsConfig)]),
     "gs_sort": (ctypes.c_int, [P(GsInstances), ctypes.c_int64, P(GsConfig), ctypes.c_void_p,
-                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                               ctypes.c_void_p]),
     "gs_render_fwd": (ctypes.c_int, [P(GsProjected), P(GsInstances), ctypes.c_void_p,
-                                     P(GsCamera), ctypes.c_int32, P(GsConfig), ctypes.c_void_p,
+                                     ctypes.c_void_p, P(GsCamera), ctypes.c_int32, P(GsConfig),
+                                     ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p]),
     "gs_render_bwd": (ctypes.c_int, [P(GsProjected), P(GsInstances), ctypes.c_void_p,
-                                     P(GsCamera), ctypes.c_int32, P(GsConfig), ctypes.c_void_p,
+                                     ctypes.c_void_p, P(GsCamera), ctypes.c_int32, P(GsConfig),
+                                     ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int64, ctypes.c_void_p]),
     "gs_project_bwd": (ctypes.c_int, [P(GsParams), P(GsCamera), ctypes.c_int32, P(GsConfig),

@@ -48,9 +48,13 @@ struct WaveTile {
   bool inside;
 };
 
+// Workgroup b renders tile tile_order[b] when an order is given (gs_sort writes the
+// tiles longest list first, so the heaviest tiles start first and do not form the
+// tail of the launch), else tile b.
 template <int TS>
-__device__ __forceinline__ bool wave_tile(const TileViews& tv, WaveTile& w) {
-  w.tile = blockIdx.x;
+__device__ __forceinline__ bool wave_tile(const TileViews& tv, const uint32_t* tile_order,
+                                          WaveTile& w) {
+  w.tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;
   w.n_records = tv.n_records;
   w.v = view_of_tile(tv, w.tile);
   const int lt = w.tile - tv.tile_offset[w.v];
@@ -70,12 +74,19 @@ __device__ __forceinline__ bool wave_tile(const TileViews& tv, WaveTile& w) {
   return true;
 }
 
-// Gather instance i (if i < end), test its box against the wave's block and
-// compact the kept ones into the wave's LDS slice. Returns the kept count.
+// Gather instance i (if in range), keep it if its 3-sigma ellipse can reach the
+// wave's block, and compact the kept ones into the wave's LDS slice. Returns the
+// kept count. Two tests, both exact supersets of the pixels with m <= ext^2:
+//  * the pixel box of the ellipse meets the block;
+//  * the second whitened coordinate e1 = w10 dx + w11 dy (m >= e1^2) is linear, so
+//    its extremes over the block are at the corner pixel centres: if |e1| > ext at
+//    all four with the same sign, no pixel of the block is inside. A relative slack
+//    of 1e-5 keeps the test conservative against FP32 rounding.
 __device__ __forceinline__ int stage_batch(const float* __restrict__ record,
                                            const uint32_t* __restrict__ vals, uint32_t i,
-                                           bool in_range, const WaveTile& w, float4* s_geo,
-                                           float4* s_shape, float4* s_col, uint32_t* s_gid) {
+                                           bool in_range, const WaveTile& w, float ext,
+                                           float4* s_geo, float4* s_shape, float4* s_col,
+                                           uint32_t* s_gid) {
   bool keep = false;
   float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0;
   uint32_t g = 0;
@@ -91,7 +102,15 @@ __device__ __forceinline__ int stage_batch(const float* __restrict__ record,
     keep = (ilo <= w.x1) && (ihi >= w.x0) && (jlo <= w.y1) && (jhi >= w.y0);
     if (keep) {
       r1 = rec[1];
-      r2 = rec[2];
+      const float dxa = ((float)(w.x0 - ilo) + 0.5f) - r0.z, dxb = ((float)(w.x1 - ilo) + 0.5f) - r0.z;
+      const float dya = ((float)(w.y0 - jlo) + 0.5f) - r0.w, dyb = ((float)(w.y1 - jlo) + 0.5f) - r0.w;
+      const float ea = fmaf(r1.y, dxa, r1.z * dya), eb = fmaf(r1.y, dxb, r1.z * dya);
+      const float ec = fmaf(r1.y, dxa, r1.z * dyb), ed = fmaf(r1.y, dxb, r1.z * dyb);
+      const float lim = ext * 1.00001f;
+      const float emin = fminf(fminf(ea, eb), fminf(ec, ed));
+      const float emax = fmaxf(fmaxf(ea, eb), fmaxf(ec, ed));
+      keep = !(emin > lim || emax < -lim);
+      if (keep) r2 = rec[2];
     }
   }
   const uint64_t km = __ballot(keep);
@@ -110,15 +129,15 @@ __device__ __forceinline__ int stage_batch(const float* __restrict__ record,
 template <int TS>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
-                  const uint32_t* __restrict__ ranges, TileViews tv, Rules rules,
-                  float* __restrict__ image, float* __restrict__ T_final,
-                  int32_t* __restrict__ last_idx) {
+                  const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
+                  TileViews tv, Rules rules, float* __restrict__ image,
+                  float* __restrict__ T_final, int32_t* __restrict__ last_idx) {
   constexpr int WPT = (TS / 8) * (TS / 8);
   __shared__ float4 s_geo[WPT][kWave];
   __shared__ float4 s_shape[WPT][kWave];
   __shared__ float4 s_col[WPT][kWave];
   WaveTile w;
-  if (!wave_tile<TS>(tv, w)) return;
+  if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint32_t start = ranges[2 * w.tile], end = ranges[2 * w.tile + 1];
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
@@ -128,8 +147,8 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   for (uint32_t base = start; base < end; base += kWave) {
     if (__ballot(!done) == 0ull) break;
     const uint32_t i = base + lane;
-    const int cnt = stage_batch(record, vals, i, i < end, w, s_geo[wave], s_shape[wave],
-                                s_col[wave], nullptr);
+    const int cnt = stage_batch(record, vals, i, i < end, w, rules.ext, s_geo[wave],
+                                s_shape[wave], s_col[wave], nullptr);
     for (int k = 0; k < cnt; ++k) {
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
@@ -207,16 +226,17 @@ __device__ __forceinline__ float wave_reduce9_transposed(float a0, float a1, flo
 template <int TS>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
-                  const uint32_t* __restrict__ ranges, TileViews tv, Rules rules,
-                  const float* __restrict__ T_final, const int32_t* __restrict__ last_idx,
-                  const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
+                  const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
+                  TileViews tv, Rules rules, const float* __restrict__ T_final,
+                  const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimage,
+                  float* __restrict__ grad2d) {
   constexpr int WPT = (TS / 8) * (TS / 8);
   __shared__ float4 s_geo[WPT][kWave];
   __shared__ float4 s_shape[WPT][kWave];
   __shared__ float4 s_col[WPT][kWave];
   __shared__ uint32_t s_gid[WPT][kWave];
   WaveTile w;
-  if (!wave_tile<TS>(tv, w)) return;
+  if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint32_t start = ranges[2 * w.tile];
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
@@ -239,7 +259,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   for (int64_t top = wave_last; top >= (int64_t)start; top -= kWave) {
     const int64_t bot = max((int64_t)start, top - (kWave - 1));
     const int64_t i = bot + lane;
-    const int cnt = stage_batch(record, vals, (uint32_t)i, i <= top, w, s_geo[wave],
+    const int cnt = stage_batch(record, vals, (uint32_t)i, i <= top, w, rules.ext, s_geo[wave],
                                 s_shape[wave], s_col[wave], s_gid[wave]);
     for (int k = cnt - 1; k >= 0; --k) {
       const float4 geo = s_geo[wave][k];
@@ -327,7 +347,8 @@ static int render_common(const gs_projected* proj, const gs_instances* inst,
 }
 
 extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
-                             const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                             const uint32_t* tile_ranges, const uint32_t* tile_order,
+                             const gs_camera* cams, int32_t n_views,
                              const gs_config* cfg, float* image, float* T_final, int32_t* last_idx,
                              int64_t n, gs_stream_t stream) {
   TileViews tv;
@@ -339,15 +360,15 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
   switch (cfg->tile_size) {
     case 8:
-      render_fwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+      render_fwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
                                                image, T_final, last_idx);
       break;
     case 32:
-      render_fwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tv,
+      render_fwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv,
                                                   rules, image, T_final, last_idx);
       break;
     default:
-      render_fwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+      render_fwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
                                                  image, T_final, last_idx);
       break;
   }
@@ -371,7 +392,8 @@ extern "C" int gs_loss_l1(const float* image, const float* target, const gs_came
 }
 
 extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
-                             const uint32_t* tile_ranges, const gs_camera* cams, int32_t n_views,
+                             const uint32_t* tile_ranges, const uint32_t* tile_order,
+                             const gs_camera* cams, int32_t n_views,
                              const gs_config* cfg, const float* T_final, const int32_t* last_idx,
                              const float* dL_dimage, float* grad2d, int64_t n,
                              gs_stream_t stream) {
@@ -384,15 +406,15 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
   switch (cfg->tile_size) {
     case 8:
-      render_bwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+      render_bwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
                                                T_final, last_idx, dL_dimage, grad2d);
       break;
     case 32:
-      render_bwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tv,
+      render_bwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv,
                                                   rules, T_final, last_idx, dL_dimage, grad2d);
       break;
     default:
-      render_bwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tv, rules,
+      render_bwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
                                                  T_final, last_idx, dL_dimage, grad2d);
       break;
   }

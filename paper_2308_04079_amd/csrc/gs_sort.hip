@@ -255,6 +255,34 @@ sort_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ coun
   ranges[2 * t + 1] = (uint32_t)lower((uint64_t)(t + 1) << 32);
 }
 
+// Issue order for the render launches: tiles bucketed by floor(log2(list length)),
+// longest bucket first (order inside a bucket is arbitrary; it changes no result).
+__device__ __forceinline__ int length_bucket(uint32_t len) { return len ? 32 - __clz(len) : 0; }
+
+__global__ void __launch_bounds__(1024)
+sort_tile_order(const uint32_t* __restrict__ ranges, int64_t n_tiles, uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[33];
+  const int t = threadIdx.x;
+  if (t < 33) cnt[t] = 0;
+  __syncthreads();
+  for (int64_t i = t; i < n_tiles; i += 1024)
+    atomicAdd(&cnt[length_bucket(ranges[2 * i + 1] - ranges[2 * i])], 1u);
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int b = 32; b >= 0; --b) {
+      const uint32_t c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int64_t i = t; i < n_tiles; i += 1024) {
+    const uint32_t pos = atomicAdd(&cnt[length_bucket(ranges[2 * i + 1] - ranges[2 * i])], 1u);
+    order[pos] = (uint32_t)i;
+  }
+}
+
 }  // namespace gs
 
 using namespace gs;
@@ -269,8 +297,8 @@ extern "C" size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_tota
 }
 
 extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
-                       uint32_t* tile_ranges, void* workspace, size_t workspace_bytes,
-                       gs_stream_t stream) {
+                       uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
+                       size_t workspace_bytes, gs_stream_t stream) {
   if (!inst || !cfg || !tile_ranges || !workspace || n_tiles_total < 1) return GS_ERR_ARG;
   int rc = check_config(cfg);
   if (rc != GS_OK) return rc;
@@ -317,5 +345,6 @@ extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs
   }
   sort_ranges<<<dim3((unsigned)((n_tiles_total + 255) / 256)), 256, 0, s>>>(
       inst->keys, inst->count, cap, n_tiles_total, tile_ranges);
+  if (tile_order) sort_tile_order<<<1, 1024, 0, s>>>(tile_ranges, n_tiles_total, tile_order);
   return launch_status();
 }

@@ -69,6 +69,7 @@ class RenderState:
     status: torch.Tensor
     capacity: int
     ranges: torch.Tensor
+    order: torch.Tensor       # tile issue order (longest list first)
     image: torch.Tensor       # flat: per view [3][H][W] at 3 * pix_offset[v]
     T_final: torch.Tensor     # flat: per view [H][W] at pix_offset[v]
     last_idx: torch.Tensor
@@ -143,6 +144,7 @@ class Rasterizer:
                                                 ctypes.byref(proj), stream))
         cap = self.capacity if self.capacity is not None else max(1 << 16, 2 * n * V)
         ranges = torch.empty(2 * n_tiles, dtype=torch.int32, device=dev)
+        order = torch.empty(n_tiles, dtype=torch.int32, device=dev)
         image = torch.empty(3 * pix[-1], dtype=torch.float32, device=dev)
         T_final = torch.empty(pix[-1], dtype=torch.float32, device=dev)
         last_idx = torch.empty(pix[-1], dtype=torch.int32, device=dev)
@@ -158,7 +160,7 @@ class Rasterizer:
             status = torch.zeros(1, dtype=torch.int32, device=dev)
             state = RenderState(n, cams, cams_c, V, int(n_tiles), list(toff), pix, depth_key,
                                 tiles_touched, record, keys, vals, keys_alt, vals_alt, count,
-                                status, cap, ranges, image, T_final, last_idx)
+                                status, cap, ranges, order, image, T_final, last_idx)
             inst = state.instances()
             _lib.check("gs_bin", lib.gs_bin(ctypes.byref(proj), n, cams_c, V, cfg,
                                             ctypes.byref(inst), _lib.ptr(bin_ws),
@@ -166,11 +168,11 @@ class Rasterizer:
             sort_bytes = lib.gs_sort_workspace_bytes(cap, n_tiles, cfg)
             sort_ws = torch.empty(max(1, sort_bytes), dtype=torch.uint8, device=dev)
             _lib.check("gs_sort", lib.gs_sort(ctypes.byref(inst), n_tiles, cfg,
-                                              _lib.ptr(ranges), _lib.ptr(sort_ws),
+                                              _lib.ptr(ranges), _lib.ptr(order), _lib.ptr(sort_ws),
                                               sort_ws.numel(), stream))
             _lib.check("gs_render_fwd", lib.gs_render_fwd(
-                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(ranges), cams_c, V, cfg,
-                _lib.ptr(image), _lib.ptr(T_final), _lib.ptr(last_idx), n, stream))
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(ranges), _lib.ptr(order), cams_c,
+                V, cfg, _lib.ptr(image), _lib.ptr(T_final), _lib.ptr(last_idx), n, stream))
             if not check:
                 break
             st, ct = state.read_status()
@@ -200,7 +202,8 @@ class Rasterizer:
         proj = state.projected()
         inst = state.instances()
         _lib.check("gs_render_bwd", lib.gs_render_bwd(
-            ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(state.ranges), state.cams_c, V, cfg,
+            ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(state.ranges), _lib.ptr(state.order),
+            state.cams_c, V, cfg,
             _lib.ptr(state.T_final), _lib.ptr(state.last_idx), _lib.ptr(dL_dimage),
             _lib.ptr(grad2d), n, stream))
         grads = {k: torch.empty_like(getattr(params, k))

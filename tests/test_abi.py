@@ -86,7 +86,7 @@ def test_host_argument_checks_return_before_any_launch(L):
     inst = L.GsInstances(0, 0, 0, 0, 0, 0, 0)
     assert lib.gs_bin(ctypes.byref(proj), 1, many, 33, ctypes.byref(cfg), ctypes.byref(inst), None, 0, None) in (L.ERR_ARG, L.ERR_UNSUPPORTED)
     huge = L.make_cameras([scenes.pinhole_camera(40000, 8)])
-    assert lib.gs_render_fwd(ctypes.byref(proj), ctypes.byref(inst), 1, huge, 1, ctypes.byref(cfg), 1, 1, 1, 1, None) == L.ERR_UNSUPPORTED
-    assert lib.gs_sort(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, 0, None) == L.ERR_ARG
+    assert lib.gs_render_fwd(ctypes.byref(proj), ctypes.byref(inst), 1, None, huge, 1, ctypes.byref(cfg), 1, 1, 1, 1, None) == L.ERR_UNSUPPORTED
+    assert lib.gs_sort(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, None, 0, None) == L.ERR_ARG
     assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) > (1 << 20) // 4096 * 6 * 1024
     assert lib.gs_status_string(L.ERR_CAPACITY) == b"instance count exceeds capacity"
