@@ -190,34 +190,39 @@ __device__ __forceinline__ int wave_max_int(int x) {
   return x;
 }
 
-// Sum over the 16 lanes of each DPP row; the row sum lands in every lane of the row.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, true));
-  return v;
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                                0xF, 0xF, true));
 }
 
-// Reduce nine per-lane values over the wave and leave value k's wave total in
-// lanes k, k + 16, k + 32, k + 48 (k < 9): row sums by DPP, a lane-select so that
-// in-row position k carries value k, then two cross-row exchanges of that one value.
-__device__ __forceinline__ float wave_reduce9_transposed(float a0, float a1, float a2, float a3,
-                                                         float a4, float a5, float a6, float a7,
-                                                         float a8) {
-  a0 = row_sum16(a0); a1 = row_sum16(a1); a2 = row_sum16(a2);
-  a3 = row_sum16(a3); a4 = row_sum16(a4); a5 = row_sum16(a5);
-  a6 = row_sum16(a6); a7 = row_sum16(a7); a8 = row_sum16(a8);
-  const int k = __lane_id() & 15;
-  float v = a8;
-  v = (k == 7) ? a7 : v;
-  v = (k == 6) ? a6 : v;
-  v = (k == 5) ? a5 : v;
-  v = (k == 4) ? a4 : v;
-  v = (k == 3) ? a3 : v;
-  v = (k == 2) ? a2 : v;
-  v = (k == 1) ? a1 : v;
-  v = (k == 0) ? a0 : v;
+// Wave sum of nine per-lane values as a reduce-scatter butterfly inside each 16-lane
+// DPP row: at every step a lane keeps half of its remaining values and adds its
+// partner's copy of them (9 -> 5 -> 3 -> 2 -> 1 registers). The mirror patterns
+// pair lanes that differ in all low bits, so they come first (split on bit 3, then
+// bit 2), then xor 2 and xor 1. Two cross-row exchanges finish the sum. In-row lane
+// l then holds the total of value kReduceIndex(l) when bit l of kReduceLanes is set.
+constexpr uint32_t kReduceLanes = 0x1737u;  // row lanes 0, 1, 2, 4, 5, 8, 9, 10, 12
+__device__ __forceinline__ int reduce_index(uint32_t l) {
+  return 5 * ((l >> 3) & 1) + 3 * ((l >> 2) & 1) + 2 * ((l >> 1) & 1) + (l & 1);
+}
+
+__device__ __forceinline__ float wave_reduce9_scatter(float a0, float a1, float a2, float a3,
+                                                      float a4, float a5, float a6, float a7,
+                                                      float a8) {
+  const uint32_t l = __lane_id() & 15;
+  const bool h3 = l & 8, h2 = l & 4, h1 = l & 2, h0 = l & 1;
+  const float x0 = (h3 ? a5 : a0) + dpp_row<0x140>(h3 ? a0 : a5);
+  const float x1 = (h3 ? a6 : a1) + dpp_row<0x140>(h3 ? a1 : a6);
+  const float x2 = (h3 ? a7 : a2) + dpp_row<0x140>(h3 ? a2 : a7);
+  const float x3 = (h3 ? a8 : a3) + dpp_row<0x140>(h3 ? a3 : a8);
+  const float x4 = (h3 ? 0.0f : a4) + dpp_row<0x140>(h3 ? a4 : 0.0f);
+  const float y0 = (h2 ? x3 : x0) + dpp_row<0x141>(h2 ? x0 : x3);
+  const float y1 = (h2 ? x4 : x1) + dpp_row<0x141>(h2 ? x1 : x4);
+  const float y2 = (h2 ? 0.0f : x2) + dpp_row<0x141>(h2 ? x2 : 0.0f);
+  const float z0 = (h1 ? y2 : y0) + dpp_row<0x4E>(h1 ? y0 : y2);
+  const float z1 = (h1 ? 0.0f : y1) + dpp_row<0x4E>(h1 ? y1 : 0.0f);
+  float v = (h0 ? z1 : z0) + dpp_row<0xB1>(h0 ? z0 : z1);
   v += __shfl_xor(v, 16, kWave);
   v += __shfl_xor(v, 32, kWave);
   return v;
@@ -253,9 +258,13 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
     g1 = dimg[HW + p];
     g2 = dimg[2 * HW + p];
   }
-  float B0 = T * rules.bg[0], B1 = T * rules.bg[1], B2 = T * rules.bg[2];
+  // only g . B is ever needed, where B is the colour accumulated behind the current
+  // Gaussian (initially T_final bg): dC/dalpha_i . g = T_i (g . c_i) - (g . B_i) / (1 - alpha_i)
+  float S = T * (g0 * rules.bg[0] + g1 * rules.bg[1] + g2 * rules.bg[2]);
   const int wave_last = wave_max_int(last);
   if (wave_last < (int)start) return;  // no pixel of this wave blended anything
+  const bool atomic_lane = lane < 16 && ((kReduceLanes >> lane) & 1u);
+  const int atomic_slot = reduce_index((uint32_t)lane);
   for (int64_t top = wave_last; top >= (int64_t)start; top -= kWave) {
     const int64_t bot = max((int64_t)start, top - (kWave - 1));
     const int64_t i = bot + lane;
@@ -274,25 +283,23 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       T = T * inv;  // transmittance in front of this Gaussian
       const float wgt = contrib ? T * e.alpha : 0.0f;
       const float d_r = wgt * g0, d_g = wgt * g1, d_b = wgt * g2;
-      float dalpha = g0 * (T * col.x - B0 * inv) + g1 * (T * col.y - B1 * inv) +
-                     g2 * (T * col.z - B2 * inv);
-      B0 = fmaf(wgt, col.x, B0);
-      B1 = fmaf(wgt, col.y, B1);
-      B2 = fmaf(wgt, col.z, B2);
+      const float gc = fmaf(g2, col.z, fmaf(g1, col.y, g0 * col.x));
+      float dalpha = fmaf(T, gc, -S * inv);
+      S = fmaf(wgt, gc, S);
       // alpha = min(alpha_max, o G): no gradient through a clamped alpha
       dalpha = (contrib && shape.w * e.G <= rules.alpha_max) ? dalpha : 0.0f;
       const float d_o = dalpha * e.G;
-      const float dm = -0.5f * dalpha * e.alpha;
-      const float t0 = 2.0f * dm * e.e0, t1 = 2.0f * dm * e.e1;
-      // m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = pixel - mean
-      const float d_mx = -(t0 * shape.x + t1 * shape.y);
+      // dalpha/dm = -alpha / 2; m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = pixel - mean
+      const float q = -dalpha * e.alpha;
+      const float t0 = q * e.e0, t1 = q * e.e1;
+      const float d_mx = -fmaf(t0, shape.x, t1 * shape.y);
       const float d_my = -(t1 * shape.z);
       const float d_w00 = t0 * e.dx, d_w10 = t1 * e.dx, d_w11 = t1 * e.dy;
       if (__ballot(contrib) != 0ull) {
-        const float tot = wave_reduce9_transposed(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r,
-                                                  d_g, d_b);
-        if (lane < GS_GRAD2D_FLOATS)
-          atomicAdd(grad2d + (size_t)s_gid[wave][k] * GS_GRAD2D_FLOATS + lane, tot);
+        const float tot = wave_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g,
+                                               d_b);
+        if (atomic_lane)
+          atomicAdd(grad2d + (size_t)s_gid[wave][k] * GS_GRAD2D_FLOATS + atomic_slot, tot);
       }
     }
     __builtin_amdgcn_wave_barrier();
