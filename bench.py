@@ -2,12 +2,14 @@
 
 One step = the whole hot path over one batch of views: project -> bin -> sort ->
 blend forward -> L1 loss gradient -> blend backward -> projection backward, on
-seeded synthetic inputs resident in HBM (3M Gaussians of the clustered-scene
+seeded synthetic inputs resident in HBM (default: 3M Gaussians of the clustered-scene
 generator, SH degree 3, four 1920x1080 orbit cameras; targets rendered once from a
-jittered copy of the scene). ``value`` is the batched rate (all views of a step in
-one call per stage); the same step done one view at a time is reported beside it.
+jittered copy of the scene). ``value`` is the batched rate: all views of a step in one
+call per stage, the step captured as one HIP graph. Beside it: the same batched step
+launched eagerly, and the step done one view at a time (eager, and one graph per view).
 
 Prints one JSON line (rank 0). Runs on one GPU: --gpus above 1 exits with a message.
+``--mode train`` runs the Adam training loop instead (steps/s and peak HBM).
 """
 from __future__ import annotations
 
@@ -27,15 +29,30 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
+WORKLOAD_TEXT = {
+    "train4": "clustered scene, {n} Gaussians, SH3, {v} orbit views of 1920x1080 per step, "
+              "fwd+bwd with L1 loss, batched: all views in one call per stage, one HIP graph "
+              "per step",
+    "full1080": "clustered scene, {n} Gaussians, SH3, one 1920x1080 view at the origin, "
+                "fwd+bwd with L1 loss, one HIP graph per step",
+    "multiview": "clustered scene, {n} Gaussians, SH3, {v} orbit views of mixed resolution "
+                 "(640x360 to 1920x1080), fwd+bwd with L1 loss, batched, one HIP graph per step",
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--views", type=int, default=4)
-    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--n", type=int, default=None, help="Gaussians (default: the workload's)")
+    ap.add_argument("--workload", choices=("train4", "full1080", "multiview"), default="train4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--mode", choices=("views", "train"), default="views",
+                    help="views: the fwd+bwd views/s metric (default); train: the Adam training "
+                         "loop over 4-view minibatches (steps/s and peak HBM)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -47,12 +64,14 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if args.mode == "train":
+        return train(args)
     import numpy as np
     import torch
 
     import scenes
     from paper_2308_04079_amd import GaussianParams, Rasterizer
-    from paper_2308_04079_amd.raster import l1_loss_grad
+    from paper_2308_04079_amd.raster import GraphStep, l1_loss_grad
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -60,15 +79,17 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
 
     t0 = time.time()
-    sc = scenes.clustered_scene(args.n, 4, 3)
-    cams = scenes.orbit_cameras(args.views, 4, resolutions=((1920, 1080),))
+    sc, cams = scenes.workload(args.workload, args.n)
+    if args.workload == "train4" and args.views != 4:
+        cams = scenes.orbit_cameras(args.views, 4, resolutions=((1920, 1080),))
     target_sc = scenes.jitter_means(sc, 4)
     params = GaussianParams.from_numpy(sc, dev)
     tparams = GaussianParams.from_numpy(target_sc, dev)
     del target_sc
-    log(f"[bench] scene ready in {time.time() - t0:.1f}s: N={sc.n}, {len(cams)} views")
+    V = len(cams)
+    log(f"[bench] scene ready in {time.time() - t0:.1f}s: N={sc.n}, {V} views")
 
-    rast = Rasterizer(sh_degree=3)
+    rast = Rasterizer(sh_degree=sc.sh_degree)
     tstate = rast.render(tparams, cams)             # sizes the capacity and renders targets
     target = tstate.image.clone()
     del tstate, tparams
@@ -76,66 +97,78 @@ def main():
     st, count = probe.read_status()
     rast.capacity = int(count * 1.15) + 4096
     del probe
-    V = len(cams)
     zero_loss = torch.zeros(V, dtype=torch.float32, device=dev)
 
-    def step(rs, cam_list, tgt, ev=None):
-        def mark(name):
-            if ev is not None:
-                e = torch.cuda.Event(enable_timing=True)
-                e.record()
-                ev.append((name, e))
-        mark("start")
+    def step(rs, cam_list, tgt):
         state = rs.render(params, cam_list, check=False)
-        mark("forward")
         loss = zero_loss[:len(cam_list)].clone()
         dL = l1_loss_grad(state, tgt, loss)
-        mark("loss")
         grads, _ = rs.backward(params, state, dL)
-        mark("backward")
         return state, grads, loss
 
-    # per-stage timing uses events between the library calls of one extra step
+    def timed(fn, steps, dist=None):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if dist is not None else []
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for k in range(steps):
+            if evs:
+                evs[k].record()
+            out = fn()
+        if evs:
+            evs[steps].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - a
+        if evs:
+            dist.extend(evs[k].elapsed_time(evs[k + 1]) for k in range(steps))
+        return out, wall
+
+    # headline: the whole batched step as one HIP graph launch
+    gstep = GraphStep(rast, params, cams, target, warmup=max(args.warmup, 1))
     for _ in range(args.warmup):
-        state, grads, loss = step(rast, cams, target)
-    torch.cuda.synchronize()
-    if args.warmup > 0:
-        st, count = state.read_status()
-        assert st == 0, f"device status {st} after warm-up"
-    log(f"[bench] warm-up done: M={count} instances for {V} views")
-
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        state, grads, loss = step(rast, cams, target)
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    st, _ = state.read_status()
+        gstep.replay()
+    step_ms = []
+    (state, grads, loss), dt = timed(gstep.replay, args.steps, step_ms)
+    st, count = state.read_status()
     assert st == 0, f"device status {st} in the timed region"
-    ms_per_step = (t_end - t_start) * 1000.0 / args.steps
-    views_per_s = V * args.steps / (t_end - t_start)
-    log(f"[bench] batched: {ms_per_step:.2f} ms/step, {views_per_s:.1f} views/s")
+    ms_per_step = dt * 1000.0 / args.steps
+    views_per_s = V * args.steps / dt
+    log(f"[bench] batched, one graph per step: {ms_per_step:.2f} ms/step, {views_per_s:.1f} views/s"
+        f" (M={count} instances)")
 
-    # kernel-level timing of the dominant kernels, with events on the launch stream
+    # the same batched step launched eagerly, call by call
+    for _ in range(args.warmup):
+        step(rast, cams, target)
+    _, dt_e = timed(lambda: step(rast, cams, target), args.steps)
+    eager_views = V * args.steps / dt_e
+    log(f"[bench] batched, eager launches: {eager_views:.1f} views/s")
+
+    # kernel-level timing of every library call, with events on the launch stream
     stages = time_stages(rast, params, cams, target, args.steps, zero_loss)
     log("[bench] stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stages["ms"].items()))
 
-    per_view = None
+    per_view = per_view_graph = None
     if not args.no_per_view:
-        prast = Rasterizer(sh_degree=3, capacity=rast.capacity)
+        prast = Rasterizer(sh_degree=sc.sh_degree, capacity=rast.capacity)
         tviews = [target[3 * state.pix_offset[v]:3 * state.pix_offset[v + 1]] for v in range(V)]
+
+        def per_view_step():
+            for v in range(V):
+                step(prast, [cams[v]], tviews[v])
         for _ in range(args.warmup):
-            for v in range(V):
-                step(prast, [cams[v]], tviews[v])
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(args.steps):
-            for v in range(V):
-                step(prast, [cams[v]], tviews[v])
-        torch.cuda.synchronize()
-        b = time.perf_counter()
-        per_view = V * args.steps / (b - a)
-        log(f"[bench] per-view: {per_view:.1f} views/s")
+            per_view_step()
+        _, dt_p = timed(per_view_step, args.steps)
+        per_view = V * args.steps / dt_p
+        graphs = [GraphStep(prast, params, [cams[v]], tviews[v]) for v in range(V)]
+
+        def per_view_graph_step():
+            for g in graphs:
+                g.replay()
+        for _ in range(args.warmup):
+            per_view_graph_step()
+        _, dt_pg = timed(per_view_graph_step, args.steps)
+        per_view_graph = V * args.steps / dt_pg
+        del graphs
+        log(f"[bench] per-view: {per_view:.1f} views/s eager, {per_view_graph:.1f} views/s graphs")
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -147,6 +180,9 @@ def main():
         del src, dst
 
     roof = roofline(stages, state, count, sc.n, V)
+    hbm = hbm_rates(stages["ms"], stages["state"], count, sc.n, V, (sc.sh_degree + 1) ** 2,
+                    rast.cfg.sort_digit_bits)
+    q = np.percentile(np.array(step_ms), [10, 50, 90])
     cpu = None if args.no_cpu_baseline else cpu_baseline(log)
 
     out = {
@@ -162,16 +198,89 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"clustered scene, {sc.n} Gaussians, SH3, {V}x1920x1080 orbit "
-                               "views per step, fwd+bwd with L1 loss, batched (one call per stage)",
-                   "gaussians": sc.n, "views_per_step": V, "width": 1920, "height": 1080,
-                   "tile": 16, "sort_digit_bits": 8, "instances": count},
+        "config": {"workload": WORKLOAD_TEXT[args.workload].format(n=sc.n, v=V),
+                   "gaussians": sc.n, "views_per_step": V,
+                   "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
+                   "tile": 16, "sort_digit_bits": 8, "lds_batch": 64, "instances": count},
+        "batched_eager_value": round(eager_views, 3),
         "per_view_value": None if per_view is None else round(per_view, 3),
+        "per_view_graph_value": None if per_view_graph is None else round(per_view_graph, 3),
+        "step_ms_p10_p50_p90": [round(float(x), 4) for x in q],
         "stage_ms": {k: round(v, 4) for k, v in stages["ms"].items()},
+        "stage_hbm": hbm,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def train(args):
+    """Training loop through torch.autograd: 3M Gaussians, SH3, FP32 parameters and
+    FP32 Adam state (lr 1e-3, betas 0.9/0.999, eps 1e-8 for every group), 4 distinct
+    1920x1080 views per step drawn (seeded) from a pool of 64 orbit cameras, L1 loss
+    against targets rendered once from a jittered copy of the scene."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2308_04079_amd import GaussianParams, Rasterizer, rasterize
+
+    dev = torch.device("cuda:0")
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    sc = scenes.clustered_scene(args.n or 3_000_000, 4, 3)
+    pool = scenes.orbit_cameras(64, 40, resolutions=((1920, 1080),))
+    tparams = GaussianParams.from_numpy(scenes.jitter_means(sc, 4), dev)
+    rast = Rasterizer(sh_degree=3)
+    targets = []
+    for cam in pool:
+        st = rast.render(tparams, [cam])
+        targets.append(st.image.clone())
+    del tparams, st
+    cap_probe = max(rast.render(GaussianParams.from_numpy(sc, dev), pool[:4]).read_status()[1], 1)
+    rast.capacity = int(cap_probe * 1.5) + 4096
+    p0 = GaussianParams.from_numpy(sc, dev)
+    leaves = [getattr(p0, k).clone().requires_grad_(True)
+              for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
+    del p0
+    opt = torch.optim.Adam(leaves, lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    rng = np.random.default_rng(41)
+    batches = [rng.choice(len(pool), 4, replace=False) for _ in range(args.warmup + args.steps)]
+
+    def step(idx):
+        cams = [pool[i] for i in idx]
+        img = rasterize(rast, cams, *leaves)
+        tgt = torch.cat([targets[i] for i in idx])
+        per_view = [(img[3 * o:3 * e] - tgt[3 * o:3 * e]).abs().mean()
+                    for o, e in zip(np.arange(4) * 1920 * 1080, np.arange(1, 5) * 1920 * 1080)]
+        loss = torch.stack(per_view).sum()
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        return loss
+
+    for k in range(args.warmup):
+        step(batches[k])
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    t0 = time.perf_counter()
+    losses = []
+    for k in range(args.steps):
+        losses.append(step(batches[args.warmup + k]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    first, last = float(losses[0]), float(losses[-1])
+    log(f"[train] {args.steps} steps in {dt:.2f}s, loss {first:.5f} -> {last:.5f}")
+    print(json.dumps({
+        "metric": "training steps/sec (3M Gaussians, 4x1920x1080 views per step, fwd+bwd+Adam)",
+        "value": round(args.steps / dt, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1000 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"clustered scene, {sc.n} Gaussians, SH3, Adam over 4 of 64 "
+                               "orbit 1920x1080 views per step, L1 loss, torch.autograd",
+                   "gaussians": sc.n, "views_per_step": 4},
+        "peak_hbm_bytes": int(torch.cuda.max_memory_allocated(dev)),
+        "loss_first": first, "loss_last": last}), flush=True)
 
 
 def time_stages(rast, params, cams, target, steps, zero_loss):
@@ -339,6 +448,35 @@ def roofline(stages, state, count, n, V):
     achieved = b / (ms[dom] * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+
+
+def hbm_rates(ms, st, count, n, V, K, digit_bits):
+    """Algorithmic HBM bytes of the streaming stages and the rate each reaches.
+
+    project: parameters once (4 (11 + 3K) B per Gaussian) + depth key and tile count
+    per (view, Gaussian) + a 48 B record per visible one; bin: tile counts read twice
+    (block sums, then expansion) + the box of each visible Gaussian + 12 B per instance
+    written; sort: every pass reads and writes 12 B per instance (the minimum of any
+    sort is one such pass); project_bwd: parameters read and gradients written
+    (2 x 4 (11 + 3K) B per Gaussian), tile counts, and per visible (view, Gaussian) its
+    record and its 36 B screen-space gradient.
+    """
+    from paper_2308_04079_amd import _lib
+    vis = int((st.tiles_touched[:V * n] > 0).sum().item())
+    par = 4 * (11 + 3 * K)
+    bits = _lib.lib().gs_sort_key_bits(st.n_tiles)
+    passes = -(-bits // digit_bits)
+    b = {"project": par * n + 8 * V * n + 48 * vis,
+         "bin": 8 * V * n + 16 * vis + 12 * count,
+         "sort": 24 * count * passes,
+         "project_bwd": 2 * par * n + 4 * V * n + (48 + 36) * vis}
+    out = {}
+    for k, v in b.items():
+        gbs = v / (ms[k] * 1e-3) / 1e9
+        out[k] = {"bytes": v, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["sort"]["passes"] = passes
+    out["visible_pairs"] = vis
+    return out
 
 
 # FP32 VALU operations of one (pixel, Gaussian) evaluation as the method states it

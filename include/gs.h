@@ -90,8 +90,9 @@ typedef struct gs_config {
   float alpha_max;         /* clamp alpha to at most this, 0.99 */
   float T_min;             /* stop before transmittance falls below this, 1e-4 */
   float bg[3];             /* background colour added as T_final * bg */
-  int32_t sort_digit_bits; /* radix digit width of gs_sort: 8 */
-  int32_t reserved;        /* must be 0 */
+  int32_t sort_digit_bits; /* radix digit width of gs_sort: 4..8, default 8 */
+  int32_t lds_batch;       /* list entries each wave stages in LDS per round: 64 or 128
+                              (0 = 64); changes speed only */
 } gs_config;
 
 typedef struct gs_params {
@@ -143,7 +144,8 @@ typedef struct gs_instances {
 } gs_instances;
 
 /* Fill *cfg with the method's rules: SH degree 3, 16x16 tiles, near 0.2, 3 sigma,
- * alpha in [1/255, 0.99], T_min 1e-4, black background, 8-bit sort digits. */
+ * alpha in [1/255, 0.99], T_min 1e-4, black background, 8-bit sort digits, LDS
+ * batches of 64 entries per wave. */
 void gs_default_config(gs_config* cfg);
 
 /* Global tile ids: view v owns ids [tile_offset[v], tile_offset[v+1]) laid out
@@ -214,7 +216,7 @@ int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
  * given dL/dimage in the image layout, accumulates per view and Gaussian the
  * screen-space gradient record grad2d[v*N + g][9] =
  *   d(u, v), d(w00, w10, w11), d(opacity), d(r, g, b).
- * grad2d is zeroed by this call (in-stream) before accumulation. */
+ * The gradients are ADDED to grad2d: the caller zeroes it first. */
 int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
                   const uint32_t* tile_ranges, const uint32_t* tile_order,
                   const gs_camera* cams, int32_t n_views,
@@ -236,6 +238,74 @@ int gs_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_vie
  * image layout. */
 int gs_loss_l1(const float* image, const float* target, const gs_camera* cams, int32_t n_views,
                float* dL_dimage, float* loss, gs_stream_t stream);
+
+/* The full photometric loss of Sec. 5.1, L = (1 - lambda) L1 + lambda L_D-SSIM per
+ * view (the paper uses lambda = 0.2), with L1 as in gs_loss_l1 and L_D-SSIM =
+ * 1 - mean SSIM over the 3 H W values. SSIM (structural similarity, per channel) uses
+ * an 11 x 11 Gaussian window of standard deviation 1.5 normalised to sum 1, zero
+ * values outside the image (no renormalisation at the borders), C1 = 0.01^2,
+ * C2 = 0.03^2 (dynamic range 1); the paper names D-SSIM without these constants.
+ * Writes dL/dimage (image layout) and, if loss is not NULL, ADDS each view's loss to
+ * loss[v]. workspace: device scratch of gs_loss_workspace_bytes(cams, n_views)
+ * bytes (9 floats per pixel), owned by the caller and overwritten.
+ * lambda outside [0, 1] or a short workspace: GS_ERR_ARG. */
+size_t gs_loss_workspace_bytes(const gs_camera* cams, int32_t n_views);
+int gs_loss_photometric(const float* image, const float* target, const gs_camera* cams,
+                        int32_t n_views, float lambda, float* dL_dimage, float* loss,
+                        void* workspace, size_t workspace_bytes, gs_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Adaptive density control (Sec. 5.2, Alg. 1). Readings where the paper gives no
+ * number: the view-space positional gradient is taken in normalised device
+ * coordinates, |(W/2 dL/du, H/2 dL/dv)| per view, averaged over the views where the
+ * Gaussian was visible; a clone is an exact copy (the next optimiser step moves it);
+ * a split replaces a Gaussian by two children mu + R diag(s) z, z ~ N(0, I) given by
+ * the caller, with log-scales lowered by log(split_factor).
+ * ------------------------------------------------------------------------- */
+typedef struct gs_densify_config {
+  float grad_threshold;    /* tau_pos: densify above this average gradient, 0.0002 */
+  float min_opacity;       /* epsilon_alpha: remove below this opacity, 0.005 */
+  float split_scale;       /* split (not clone) when the largest scale exceeds this */
+  float max_world_scale;   /* remove above this largest scale; <= 0 disables */
+  float max_screen_radius; /* remove above this pixel-box half-extent; <= 0 disables */
+  float split_factor;      /* phi: scale divisor of split children, 1.6 */
+} gs_densify_config;
+
+/* grad_threshold 0.0002, min_opacity 0.005, split_scale 0.01, no size removal, phi 1.6. */
+void gs_default_densify_config(gs_densify_config* cfg);
+
+/* Statistics after a backward pass: for every Gaussian visible in some view (tiles
+ * touched > 0 in proj), ADD to grad_sum[g] the NDC gradient norms of its projected
+ * mean from grad2d (the gs_render_bwd output), to view_count[g] the number of such
+ * views, and raise max_radius[g] to its largest pixel-box half-extent. The caller
+ * zeroes the three device arrays [N] when it resets the statistics. */
+int gs_densify_accumulate(const gs_projected* proj, const float* grad2d, const gs_camera* cams,
+                          int32_t n_views, int64_t n, float* grad_sum, int32_t* view_count,
+                          float* max_radius, gs_stream_t stream);
+
+size_t gs_densify_workspace_bytes(int64_t n);
+
+/* The plan (Alg. 1): per Gaussian action[g] = 0 remove (opacity below min_opacity,
+ * or too large), 1 keep, 2 clone (average gradient above grad_threshold, largest
+ * scale at most split_scale), 3 split (above both); offsets[g] = exclusive prefix of
+ * the output counts (0, 1, 2, 2); *n_out (device) = the new Gaussian count. */
+int gs_densify_plan(const gs_params* params, const float* grad_sum, const int32_t* view_count,
+                    const float* max_radius, const gs_densify_config* cfg, uint8_t* action,
+                    uint32_t* offsets, uint32_t* n_out, void* workspace, size_t workspace_bytes,
+                    gs_stream_t stream);
+
+/* Write the new parameter arrays (layouts of gs_params with N' = n_out rows, in the
+ * gs_params_grad struct of output pointers) in Gaussian order: kept Gaussians once,
+ * clones twice, split children from normals[g][2][3]. src_index (nullable, [n_out])
+ * receives each output's source Gaussian (for gathering optimiser state). */
+int gs_densify_apply(const gs_params* params, int32_t sh_degree, const uint8_t* action,
+                     const uint32_t* offsets, const float* normals, const gs_densify_config* cfg,
+                     const gs_params_grad* out, int64_t n_out, uint32_t* src_index,
+                     gs_stream_t stream);
+
+/* Opacity reset (Sec. 5.2: every 3000 iterations): opacity <- min(opacity, max_opacity),
+ * applied to the logits in place. */
+int gs_reset_opacity(float* opacity_logits, int64_t n, float max_opacity, gs_stream_t stream);
 
 /* Copy the device status word to the host after synchronising `stream`
  * (the only synchronising call; not for use under graph capture). */

@@ -36,7 +36,7 @@ class GsConfig(ctypes.Structure):
                 ("near_z", ctypes.c_float), ("sigma_extent", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("sort_digit_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sort_digit_bits", ctypes.c_int32), ("lds_batch", ctypes.c_int32)]
 
 
 class GsParams(ctypes.Structure):
@@ -61,6 +61,12 @@ class GsInstances(ctypes.Structure):
                 ("keys_alt", ctypes.c_void_p), ("vals_alt", ctypes.c_void_p),
                 ("capacity", ctypes.c_int64), ("count", ctypes.c_void_p),
                 ("status", ctypes.c_void_p)]
+
+
+class GsDensifyConfig(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("min_opacity", ctypes.c_float),
+                ("split_scale", ctypes.c_float), ("max_world_scale", ctypes.c_float),
+                ("max_screen_radius", ctypes.c_float), ("split_factor", ctypes.c_float)]
 
 
 P = ctypes.POINTER
@@ -92,8 +98,28 @@ EXPORTS = {
     "gs_project_bwd": (ctypes.c_int, [P(GsParams), P(GsCamera), ctypes.c_int32, P(GsConfig),
                                       P(GsProjected), ctypes.c_void_p, P(GsParamsGrad),
                                       ctypes.c_void_p]),
+    "gs_loss_workspace_bytes": (ctypes.c_size_t, [P(GsCamera), ctypes.c_int32]),
+    "gs_loss_photometric": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, P(GsCamera),
+                                           ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p]),
     "gs_loss_l1": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, P(GsCamera), ctypes.c_int32,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "gs_default_densify_config": (None, [P(GsDensifyConfig)]),
+    "gs_densify_accumulate": (ctypes.c_int, [P(GsProjected), ctypes.c_void_p, P(GsCamera),
+                                             ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "gs_densify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "gs_densify_plan": (ctypes.c_int, [P(GsParams), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, P(GsDensifyConfig), ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p]),
+    "gs_densify_apply": (ctypes.c_int, [P(GsParams), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, P(GsDensifyConfig),
+                                        P(GsParamsGrad), ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "gs_reset_opacity": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float,
+                                        ctypes.c_void_p]),
     "gs_read_status": (ctypes.c_int, [P(GsInstances), P(ctypes.c_uint32), P(ctypes.c_uint32),
                                       ctypes.c_void_p]),
     "gs_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -15,7 +15,7 @@ int check_config(const gs_config* cfg) {
     return GS_ERR_ARG;
   if (!(cfg->T_min > 0.0f) || !(cfg->T_min < 1.0f)) return GS_ERR_ARG;
   if (cfg->sort_digit_bits < 4 || cfg->sort_digit_bits > 8) return GS_ERR_ARG;
-  if (cfg->reserved != 0) return GS_ERR_ARG;
+  if (cfg->lds_batch != 0 && cfg->lds_batch != 64 && cfg->lds_batch != 128) return GS_ERR_ARG;
   for (int c = 0; c < 3; ++c)
     if (!isfinite(cfg->bg[c])) return GS_ERR_ARG;
   return GS_OK;
@@ -112,6 +112,7 @@ extern "C" void gs_default_config(gs_config* cfg) {
   cfg->alpha_max = 0.99f;
   cfg->T_min = 1e-4f;
   cfg->sort_digit_bits = 8;
+  cfg->lds_batch = 64;
 }
 
 extern "C" int64_t gs_tile_layout(const gs_camera* cams, int32_t n_views, int32_t tile_size,

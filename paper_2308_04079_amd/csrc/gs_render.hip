@@ -74,81 +74,117 @@ __device__ __forceinline__ bool wave_tile(const TileViews& tv, const uint32_t* t
   return true;
 }
 
-// Gather instance i (if in range), keep it if its 3-sigma ellipse can reach the
-// wave's block, and compact the kept ones into the wave's LDS slice. Returns the
-// kept count. Two tests, both exact supersets of the pixels with m <= ext^2:
+// One list entry as gathered by a lane: kept if its 3-sigma ellipse can reach the
+// wave's block. Two tests, both exact supersets of the pixels with m <= ext^2:
 //  * the pixel box of the ellipse meets the block;
 //  * the second whitened coordinate e1 = w10 dx + w11 dy (m >= e1^2) is linear, so
 //    its extremes over the block are at the corner pixel centres: if |e1| > ext at
 //    all four with the same sign, no pixel of the block is inside. A relative slack
 //    of 1e-5 keeps the test conservative against FP32 rounding.
-__device__ __forceinline__ int stage_batch(const float* __restrict__ record,
-                                           const uint32_t* __restrict__ vals, uint32_t i,
-                                           bool in_range, const WaveTile& w, float ext,
-                                           float4* s_geo, float4* s_shape, float4* s_col,
-                                           uint32_t* s_gid) {
-  bool keep = false;
-  float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0;
-  uint32_t g = 0;
-  int ilo = 0, jlo = 0;
-  if (in_range) g = vals[i];
-  if (in_range && g < w.n_records) {
-    const float4* rec = reinterpret_cast<const float4*>(record + (size_t)g * GS_RECORD_FLOATS);
-    r0 = rec[0];
-    const int lo = __float_as_int(r0.x), hi = __float_as_int(r0.y);
-    ilo = lo & 0xFFFF;
-    jlo = (lo >> 16) & 0xFFFF;
+struct Entry {
+  float4 r0, r1, r2;
+  uint32_t g, i;
+  int ilo, jlo;
+  bool keep;
+};
+
+__device__ __forceinline__ void gather_entry(const float* __restrict__ record,
+                                             const uint32_t* __restrict__ vals, uint32_t i,
+                                             bool in_range, const WaveTile& w, float ext, Entry& e) {
+  e.keep = false;
+  e.i = i;
+  e.g = 0;
+  e.ilo = e.jlo = 0;
+  e.r0 = make_float4(0, 0, 0, 0);
+  e.r1 = e.r0;
+  e.r2 = e.r0;
+  if (in_range) e.g = vals[i];
+  if (in_range && e.g < w.n_records) {
+    const float4* rec = reinterpret_cast<const float4*>(record + (size_t)e.g * GS_RECORD_FLOATS);
+    e.r0 = rec[0];
+    const int lo = __float_as_int(e.r0.x), hi = __float_as_int(e.r0.y);
+    e.ilo = lo & 0xFFFF;
+    e.jlo = (lo >> 16) & 0xFFFF;
     const int ihi = hi & 0xFFFF, jhi = (hi >> 16) & 0xFFFF;
-    keep = (ilo <= w.x1) && (ihi >= w.x0) && (jlo <= w.y1) && (jhi >= w.y0);
-    if (keep) {
-      r1 = rec[1];
-      const float dxa = ((float)(w.x0 - ilo) + 0.5f) - r0.z, dxb = ((float)(w.x1 - ilo) + 0.5f) - r0.z;
-      const float dya = ((float)(w.y0 - jlo) + 0.5f) - r0.w, dyb = ((float)(w.y1 - jlo) + 0.5f) - r0.w;
-      const float ea = fmaf(r1.y, dxa, r1.z * dya), eb = fmaf(r1.y, dxb, r1.z * dya);
-      const float ec = fmaf(r1.y, dxa, r1.z * dyb), ed = fmaf(r1.y, dxb, r1.z * dyb);
+    e.keep = (e.ilo <= w.x1) && (ihi >= w.x0) && (e.jlo <= w.y1) && (jhi >= w.y0);
+    if (e.keep) {
+      e.r1 = rec[1];
+      const float mx = e.r0.z, my = e.r0.w;
+      const float dxa = ((float)(w.x0 - e.ilo) + 0.5f) - mx, dxb = ((float)(w.x1 - e.ilo) + 0.5f) - mx;
+      const float dya = ((float)(w.y0 - e.jlo) + 0.5f) - my, dyb = ((float)(w.y1 - e.jlo) + 0.5f) - my;
+      const float ea = fmaf(e.r1.y, dxa, e.r1.z * dya), eb = fmaf(e.r1.y, dxb, e.r1.z * dya);
+      const float ec = fmaf(e.r1.y, dxa, e.r1.z * dyb), ed = fmaf(e.r1.y, dxb, e.r1.z * dyb);
       const float lim = ext * 1.00001f;
       const float emin = fminf(fminf(ea, eb), fminf(ec, ed));
       const float emax = fmaxf(fmaxf(ea, eb), fmaxf(ec, ed));
-      keep = !(emin > lim || emax < -lim);
-      if (keep) r2 = rec[2];
+      e.keep = !(emin > lim || emax < -lim);
+      if (e.keep) e.r2 = rec[2];
     }
   }
-  const uint64_t km = __ballot(keep);
-  if (keep) {
-    const int slot = __popcll(km & lanemask_lt());
-    s_geo[slot] = make_float4((float)ilo, (float)jlo, r0.z, r0.w);
-    s_shape[slot] = r1;
-    s_col[slot] = make_float4(r2.x, r2.y, r2.z, __uint_as_float(i));
-    if (s_gid) s_gid[slot] = g;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  return __popcll(km);
 }
 
-template <int TS>
+// Compact the kept entries of the wave into its LDS slice from slot `slot0` on, in
+// lane order; returns the new fill level.
+__device__ __forceinline__ int commit_entries(const Entry& e, int slot0, float4* s_geo,
+                                              float4* s_shape, float4* s_col, uint32_t* s_gid) {
+  const uint64_t km = __ballot(e.keep);
+  if (e.keep) {
+    const int slot = slot0 + __popcll(km & lanemask_lt());
+    s_geo[slot] = make_float4((float)e.ilo, (float)e.jlo, e.r0.z, e.r0.w);
+    s_shape[slot] = e.r1;
+    s_col[slot] = make_float4(e.r2.x, e.r2.y, e.r2.z, __uint_as_float(e.i));
+    if (s_gid) s_gid[slot] = e.g;
+  }
+  return slot0 + __popcll(km);
+}
+
+// Stage the R * 64 consecutive list entries [first, first + 64 R), those at or below
+// `last_ok` only, into the wave's LDS slice (all gathers are issued before any
+// ballot). Returns the kept count.
+template <int R>
+__device__ __forceinline__ int stage_batch(const float* __restrict__ record,
+                                           const uint32_t* __restrict__ vals, int64_t first,
+                                           int64_t last_ok, const WaveTile& w, float ext,
+                                           float4* s_geo, float4* s_shape, float4* s_col,
+                                           uint32_t* s_gid) {
+  Entry e[R];
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = first + r * kWave + lane;
+    gather_entry(record, vals, (uint32_t)i, i <= last_ok, w, ext, e[r]);
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) cnt = commit_entries(e[r], cnt, s_geo, s_shape, s_col, s_gid);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return cnt;
+}
+
+template <int TS, int R>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
                   TileViews tv, Rules rules, float* __restrict__ image,
                   float* __restrict__ T_final, int32_t* __restrict__ last_idx) {
   constexpr int WPT = (TS / 8) * (TS / 8);
-  __shared__ float4 s_geo[WPT][kWave];
-  __shared__ float4 s_shape[WPT][kWave];
-  __shared__ float4 s_col[WPT][kWave];
+  constexpr int BATCH = R * kWave;
+  __shared__ float4 s_geo[WPT][BATCH];
+  __shared__ float4 s_shape[WPT][BATCH];
+  __shared__ float4 s_col[WPT][BATCH];
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
   const uint32_t start = ranges[2 * w.tile], end = ranges[2 * w.tile + 1];
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int32_t last = -1;
   bool done = !w.inside;
-  for (uint32_t base = start; base < end; base += kWave) {
+  for (uint32_t base = start; base < end; base += BATCH) {
     if (__ballot(!done) == 0ull) break;
-    const uint32_t i = base + lane;
-    const int cnt = stage_batch(record, vals, i, i < end, w, rules.ext, s_geo[wave],
-                                s_shape[wave], s_col[wave], nullptr);
+    const int cnt = stage_batch<R>(record, vals, base, (int64_t)end - 1, w, rules.ext,
+                                   s_geo[wave], s_shape[wave], s_col[wave], nullptr);
     for (int k = 0; k < cnt; ++k) {
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
@@ -228,7 +264,7 @@ __device__ __forceinline__ float wave_reduce9_scatter(float a0, float a1, float 
   return v;
 }
 
-template <int TS>
+template <int TS, int R>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
@@ -236,10 +272,11 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
                   const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimage,
                   float* __restrict__ grad2d) {
   constexpr int WPT = (TS / 8) * (TS / 8);
-  __shared__ float4 s_geo[WPT][kWave];
-  __shared__ float4 s_shape[WPT][kWave];
-  __shared__ float4 s_col[WPT][kWave];
-  __shared__ uint32_t s_gid[WPT][kWave];
+  constexpr int BATCH = R * kWave;
+  __shared__ float4 s_geo[WPT][BATCH];
+  __shared__ float4 s_shape[WPT][BATCH];
+  __shared__ float4 s_col[WPT][BATCH];
+  __shared__ uint32_t s_gid[WPT][BATCH];
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -265,11 +302,10 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   if (wave_last < (int)start) return;  // no pixel of this wave blended anything
   const bool atomic_lane = lane < 16 && ((kReduceLanes >> lane) & 1u);
   const int atomic_slot = reduce_index((uint32_t)lane);
-  for (int64_t top = wave_last; top >= (int64_t)start; top -= kWave) {
-    const int64_t bot = max((int64_t)start, top - (kWave - 1));
-    const int64_t i = bot + lane;
-    const int cnt = stage_batch(record, vals, (uint32_t)i, i <= top, w, rules.ext, s_geo[wave],
-                                s_shape[wave], s_col[wave], s_gid[wave]);
+  for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
+    const int64_t bot = max((int64_t)start, top - (BATCH - 1));
+    const int cnt = stage_batch<R>(record, vals, bot, top, w, rules.ext, s_geo[wave],
+                                   s_shape[wave], s_col[wave], s_gid[wave]);
     for (int k = cnt - 1; k >= 0; --k) {
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
@@ -365,20 +401,16 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
   const Rules rules = make_rules(cfg);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
+#define GS_FWD(TS, R)                                                                          \
+  render_fwd_kernel<TS, R><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                      \
+      proj->record, inst->vals, tile_ranges, tile_order, tv, rules, image, T_final, last_idx)
+  const bool two = cfg->lds_batch == 128;
   switch (cfg->tile_size) {
-    case 8:
-      render_fwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
-                                               image, T_final, last_idx);
-      break;
-    case 32:
-      render_fwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv,
-                                                  rules, image, T_final, last_idx);
-      break;
-    default:
-      render_fwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
-                                                 image, T_final, last_idx);
-      break;
+    case 8: if (two) GS_FWD(8, 2); else GS_FWD(8, 1); break;
+    case 32: if (two) GS_FWD(32, 2); else GS_FWD(32, 1); break;
+    default: if (two) GS_FWD(16, 2); else GS_FWD(16, 1); break;
   }
+#undef GS_FWD
   return launch_status();
 }
 
@@ -411,19 +443,16 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
   const Rules rules = make_rules(cfg);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
+#define GS_BWD(TS, R)                                                                          \
+  render_bwd_kernel<TS, R><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                      \
+      proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
+      dL_dimage, grad2d)
+  const bool two = cfg->lds_batch == 128;
   switch (cfg->tile_size) {
-    case 8:
-      render_bwd_kernel<8><<<grid, 64, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
-                                               T_final, last_idx, dL_dimage, grad2d);
-      break;
-    case 32:
-      render_bwd_kernel<32><<<grid, 1024, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv,
-                                                  rules, T_final, last_idx, dL_dimage, grad2d);
-      break;
-    default:
-      render_bwd_kernel<16><<<grid, 256, 0, s>>>(proj->record, inst->vals, tile_ranges, tile_order, tv, rules,
-                                                 T_final, last_idx, dL_dimage, grad2d);
-      break;
+    case 8: if (two) GS_BWD(8, 2); else GS_BWD(8, 1); break;
+    case 32: if (two) GS_BWD(32, 2); else GS_BWD(32, 1); break;
+    default: if (two) GS_BWD(16, 2); else GS_BWD(16, 1); break;
   }
+#undef GS_BWD
   return launch_status();
 }

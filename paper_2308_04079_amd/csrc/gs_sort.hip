@@ -21,6 +21,7 @@ namespace gs {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per block
+constexpr int kLookback = 16;                        // predecessors examined per step
 constexpr int kMaxPasses = 16;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
@@ -116,7 +117,7 @@ sort_pass(const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ val
   __shared__ uint32_t s_whist[WAVES][RADIX];
   __shared__ uint32_t s_local_base[RADIX];
   __shared__ uint32_t s_global_base[RADIX];
-  __shared__ uint32_t s_scan[kSortBlock];
+  __shared__ uint32_t s_scan[WAVES];
   __shared__ uint32_t s_tile;
 
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
@@ -181,39 +182,57 @@ sort_pass(const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ val
       __hip_atomic_store(mine, kFlagInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       __hip_atomic_store(mine, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // windowed look-back: load kLookback predecessors at once (independent loads, one
+      // latency), add them nearest first up to the first inclusive prefix; on a
+      // not-yet-published entry, keep what was added and re-poll from that entry
       int64_t t = tile - 1;
       uint32_t spins = 0;
-      while (t >= 0) {
-        const uint32_t w = __hip_atomic_load(lookback + t * RADIX + tid, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t flag = w & ~kValueMask;
-        if (flag == 0) {
+      bool found = false;
+      while (!found) {
+        uint32_t wv[kLookback];
+#pragma unroll
+        for (int j = 0; j < kLookback; ++j)
+          wv[j] = (t - j >= 0) ? __hip_atomic_load(lookback + (t - j) * RADIX + tid, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : kFlagInc;  // before block 0: an empty inclusive prefix
+        int j = 0;
+        for (; j < kLookback; ++j) {
+          const uint32_t flag = wv[j] & ~kValueMask;
+          if (flag == 0) break;
+          excl += wv[j] & kValueMask;
+          if (flag == kFlagInc) {
+            found = true;
+            break;
+          }
+        }
+        if (found) break;
+        t -= j;
+        if (j < kLookback) {  // entry t not published yet
           if (++spins > kSpinLimit) {  // never expected; bounded so the grid always drains
             atomicOr(status, GS_STATUS_SORT);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += w & kValueMask;
-        if (flag == kFlagInc) break;
-        --t;
       }
       __hip_atomic_store(mine, kFlagInc | ((excl + total) & kValueMask), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
     s_global_base[tid] = digit_start[tid] + excl;
   }
-  // block-local exclusive scan of the digit totals
-  s_scan[tid] = (tid < RADIX) ? total : 0u;
-  __syncthreads();
-  for (int d = 1; d < kSortBlock; d <<= 1) {
-    const uint32_t y = (tid >= d) ? s_scan[tid - d] : 0u;
-    __syncthreads();
-    s_scan[tid] += y;
-    __syncthreads();
+  // block-local exclusive scan of the digit totals: wave prefix sums, then the waves
+  uint32_t incl = (tid < RADIX) ? total : 0u;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += y;
   }
-  if (tid < RADIX) s_local_base[tid] = s_scan[tid] - total;
+  if (lane == kWave - 1) s_scan[wave] = incl;
+  __syncthreads();
+  uint32_t wbase_sum = 0;
+#pragma unroll
+  for (int w2 = 0; w2 < WAVES; ++w2) wbase_sum += (w2 < wave) ? s_scan[w2] : 0u;
+  if (tid < RADIX) s_local_base[tid] = wbase_sum + incl - total;
   __syncthreads();
   // reorder through LDS into block-sorted order
 #pragma unroll

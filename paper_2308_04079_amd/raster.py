@@ -109,11 +109,13 @@ class Rasterizer:
     """
 
     def __init__(self, sh_degree: int = 3, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
-                 capacity: int | None = None, growth: float = 1.25, sort_digit_bits: int = 8):
+                 capacity: int | None = None, growth: float = 1.25, sort_digit_bits: int = 8,
+                 lds_batch: int = 64):
         self.cfg = _lib.default_config(sh_degree=sh_degree, tile_size=tile_size, bg=bg,
-                                       sort_digit_bits=sort_digit_bits)
+                                       sort_digit_bits=sort_digit_bits, lds_batch=lds_batch)
         self.capacity = capacity
         self.growth = growth
+        self.check = True   # RasterizeFunction: read the status word after each forward
 
     # -- forward -----------------------------------------------------------------
     def render(self, params: GaussianParams, cams, check: bool = True) -> RenderState:
@@ -224,7 +226,7 @@ class RasterizeFunction(torch.autograd.Function):
     def forward(ctx, rasterizer, cams, means, log_scales, quats, opacity_logits, sh):
         params = GaussianParams(means.contiguous(), log_scales.contiguous(), quats.contiguous(),
                                 opacity_logits.contiguous(), sh.contiguous())
-        state = rasterizer.render(params, cams)
+        state = rasterizer.render(params, cams, check=rasterizer.check)
         ctx.rasterizer = rasterizer
         ctx.state = state
         ctx.params = params
@@ -247,7 +249,63 @@ def l1_loss_grad(state: RenderState, target: torch.Tensor, loss: torch.Tensor | 
     return dL
 
 
+def photometric_loss_grad(state: RenderState, target: torch.Tensor, lam: float = 0.2,
+                          loss: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """dL/dimage of (1 - lam) L1 + lam D-SSIM per view (Sec. 5.1); adds the losses to ``loss``."""
+    lib = _lib.lib()
+    dL = torch.empty_like(state.image)
+    need = lib.gs_loss_workspace_bytes(state.cams_c, state.n_views)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=state.image.device)
+    stream = torch.cuda.current_stream(state.image.device).cuda_stream
+    _lib.check("gs_loss_photometric", lib.gs_loss_photometric(
+        _lib.ptr(state.image), _lib.ptr(target), state.cams_c, state.n_views, float(lam),
+        _lib.ptr(dL), _lib.ptr(loss), _lib.ptr(workspace), workspace.numel(), stream))
+    return dL
+
+
 def rasterize(rasterizer: Rasterizer, cams, means, log_scales, quats, opacity_logits, sh):
     """Autograd entry point: flat image (per view [3][H][W], concatenated)."""
     return RasterizeFunction.apply(rasterizer, list(cams), means, log_scales, quats,
                                    opacity_logits, sh)
+
+
+class GraphStep:
+    """One step (forward, L1 loss gradient, backward) captured in a HIP graph.
+
+    Every call of the captured sequence only enqueues kernels and allocates nothing
+    outside torch's graph pool, so a replay re-runs the whole hot path with one
+    launch. Parameters and targets are read from the tensors given here: update
+    them in place between replays. After a replay, ``outputs.state.read_status()``
+    (which synchronises) reports an instance-capacity overflow; then build a new
+    GraphStep with a larger ``rasterizer.capacity``.
+    """
+
+    def __init__(self, rasterizer: Rasterizer, params: GaussianParams, cams, target: torch.Tensor,
+                 warmup: int = 2):
+        if rasterizer.capacity is None:
+            raise ValueError("set rasterizer.capacity (e.g. from one checked render) before capture")
+        self.rast = rasterizer
+        self.params = params
+        self.cams = list(cams)
+        self.target = target
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self._body()
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.state, self.grads, self.loss = self._body()
+
+    def _body(self):
+        state = self.rast.render(self.params, self.cams, check=False)
+        loss = torch.zeros(len(self.cams), dtype=torch.float32, device=state.image.device)
+        dL = l1_loss_grad(state, self.target, loss)
+        grads, _ = self.rast.backward(self.params, state, dL)
+        return state, grads, loss
+
+    def replay(self):
+        self.graph.replay()
+        return self.state, self.grads, self.loss

@@ -50,7 +50,7 @@ def test_struct_sizes_match_the_header_layout(L):
 
 def test_default_config_is_the_papers_rules(L):
     c = L.default_config()
-    assert (c.sh_degree, c.tile_size, c.sort_digit_bits) == (3, 16, 8)
+    assert (c.sh_degree, c.tile_size, c.sort_digit_bits, c.lds_batch) == (3, 16, 8, 64)
     assert abs(c.near_z - 0.2) < 1e-7 and c.sigma_extent == 3.0
     assert abs(c.alpha_min - 1 / 255) < 1e-9 and abs(c.alpha_max - 0.99) < 1e-7
     assert abs(c.T_min - 1e-4) < 1e-10 and list(c.bg) == [0.0, 0.0, 0.0]
@@ -90,3 +90,43 @@ def test_host_argument_checks_return_before_any_launch(L):
     assert lib.gs_sort(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, None, 0, None) == L.ERR_ARG
     assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) > (1 << 20) // 4096 * 6 * 1024
     assert lib.gs_status_string(L.ERR_CAPACITY) == b"instance count exceeds capacity"
+
+
+def test_densify_defaults_and_argument_checks(L):
+    lib = L.lib()
+    d = L.GsDensifyConfig()
+    lib.gs_default_densify_config(ctypes.byref(d))
+    assert (round(d.grad_threshold, 7), round(d.min_opacity, 6), round(d.split_factor, 5)) == (0.0002, 0.005, 1.6)
+    assert d.max_world_scale == 0.0 and d.max_screen_radius == 0.0
+    p = L.GsParams(0, 0, 0, 0, 0, 10)
+    bad = L.GsDensifyConfig()
+    lib.gs_default_densify_config(ctypes.byref(bad))
+    bad.split_factor = 1.0
+    n_out = ctypes.c_uint32(0)
+    ws = ctypes.create_string_buffer(64)
+    args = (None, None, None)
+    assert lib.gs_densify_plan(ctypes.byref(p), *args, ctypes.byref(bad), None, None,
+                               ctypes.byref(n_out), ws, 64, None) == L.ERR_ARG
+    assert lib.gs_densify_plan(ctypes.byref(p), *args, ctypes.byref(d), None, None,
+                               ctypes.byref(n_out), ws, 64, None) == L.ERR_ARG
+    assert lib.gs_densify_workspace_bytes(-1) == 0
+    assert lib.gs_densify_workspace_bytes(4096 * 3 + 1) == 5 * 4
+    assert lib.gs_reset_opacity(None, 10, 1.5, None) == L.ERR_ARG
+    assert lib.gs_reset_opacity(None, 10, 0.01, None) == L.ERR_ARG
+    assert lib.gs_reset_opacity(None, 0, 0.01, None) == L.OK
+    out = L.GsParamsGrad(0, 0, 0, 0, 0)
+    assert lib.gs_densify_apply(ctypes.byref(p), 4, None, None, None, ctypes.byref(d),
+                                ctypes.byref(out), 5, None, None) == L.ERR_ARG
+    assert lib.gs_densify_apply(ctypes.byref(p), 1, None, None, None, ctypes.byref(d),
+                                ctypes.byref(out), 5, None, None) == L.ERR_ARG
+
+
+def test_loss_argument_checks(L):
+    import scenes
+    lib = L.lib()
+    cc = L.make_cameras([scenes.pinhole_camera(40, 30)])
+    assert lib.gs_loss_workspace_bytes(cc, 1) == 9 * 40 * 30 * 4
+    ws = ctypes.create_string_buffer(16)
+    assert lib.gs_loss_photometric(1, 1, cc, 1, 1.5, 1, None, ws, 16, None) == L.ERR_ARG
+    assert lib.gs_loss_photometric(1, 1, cc, 1, 0.2, 1, None, ws, 16, None) == L.ERR_ARG
+    assert lib.gs_loss_photometric(None, 1, cc, 1, 0.2, 1, None, ws, 16, None) == L.ERR_ARG

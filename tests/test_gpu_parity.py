@@ -134,20 +134,20 @@ def test_forward_image_matches_oracle(name):
     compare_images(state, sc, cams)
 
 
-@pytest.mark.parametrize("tile", [8, 32])
-def test_tile_size_does_not_change_image(tile):
+@pytest.mark.parametrize("tile,batch", [(8, 64), (32, 64), (16, 128), (8, 128)])
+def test_tile_size_and_batch_depth_do_not_change_image(tile, batch):
     sc, cams = CASES["ragged"]
     _, _, s16 = gpu_render(sc, cams)
-    _, _, st = gpu_render(sc, cams, tile_size=tile)
+    _, _, st = gpu_render(sc, cams, tile_size=tile, lds_batch=batch)
     a, b = gpu_images(s16)[0], gpu_images(st)[0]
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
     compare_images(st, sc, cams, rules=Rules(tile=tile))
 
 
-def backward_case(sc, cams, seed, tiles=None):
+def backward_case(sc, cams, seed, tiles=None, **cfg):
     import torch
-    rast, params, state = gpu_render(sc, cams)
+    rast, params, state = gpu_render(sc, cams, **cfg)
     cam = cams[0]
     ref = render_tiles(project(sc, cam), tiles=tiles)
     w = np.random.default_rng(seed).standard_normal((cam.height, cam.width, 3))
@@ -159,10 +159,11 @@ def backward_case(sc, cams, seed, tiles=None):
     return grads, grad2d, gref, acc, p
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_backward_matches_oracle(name):
+@pytest.mark.parametrize("name,cfg", [(n, {}) for n in CASES] +
+                         [("offcentre", {"lds_batch": 128}), ("ragged", {"tile_size": 32})])
+def test_backward_matches_oracle(name, cfg):
     sc, cams = CASES[name]
-    grads, grad2d, gref, acc, p = backward_case(sc, cams, 5)
+    grads, grad2d, gref, acc, p = backward_case(sc, cams, 5, **cfg)
     g2 = to_np(grad2d).reshape(-1, 9)[:sc.n].astype(np.float64)
     ok = p.valid
     assert rel_l2(g2[ok, 0], acc["u"][ok]) <= TOL_GRAD
