@@ -50,33 +50,44 @@ def _dM_dq(qh, s):
 
 
 def blend_backward(proj, ids, px, py, dL_dC, rules: Rules, acc: dict):
-    """Back-to-front adjoint of one pixel set over one ordered list; accumulates into acc."""
+    """Back-to-front adjoint of one pixel set over one ordered list; accumulates into acc.
+
+    With rules.grad_limit = N > 0 a pixel passes gradient only to its N front-most
+    blended Gaussians (the other blended ones still shape the colour behind them).
+    """
     fwd = blend(proj, ids, px, py, rules, record=True)
     bg = np.asarray(rules.bg, dtype=np.float64)
     B = fwd.T_final[:, None] * bg[None, :]
-    for (pos, g, bl, Tb, alpha, G, clamped, dx, dy) in reversed(fwd.steps):
+    # front-to-back rank of each blended Gaussian at each pixel
+    ranks, seen = [], np.zeros(len(px), dtype=np.int64)
+    for step in fwd.steps:
+        ranks.append(seen.copy())
+        seen += step[2]
+    for idx in range(len(fwd.steps) - 1, -1, -1):
+        pos, g, bl, Tb, alpha, G, clamped, dx, dy = fwd.steps[idx]
         if not bl.any():
             continue
-        gC = dL_dC[bl]                      # (P', 3)
-        Ti, ai = Tb[bl], alpha[bl]
         c = proj.rgb[g]
-        acc["rgb"][g] += (Ti * ai) @ gC
-        dalpha = (gC * (Ti[:, None] * c[None, :] - B[bl] / (1.0 - ai)[:, None])).sum(1)
-        B[bl] += (Ti * ai)[:, None] * c[None, :]
-        free = ~clamped[bl]
-        if not free.any():
-            continue
-        da = dalpha[free]
-        acc["opacity"][g] += (da * G[bl][free]).sum()
-        dm = da * (-0.5 * ai[free])
-        ddx, ddy = dx[bl][free], dy[bl][free]
-        Q = proj.conic[g]
-        Qdx = Q[0, 0] * ddx + Q[0, 1] * ddy
-        Qdy = Q[1, 0] * ddx + Q[1, 1] * ddy
-        acc["u"][g] += (dm * (-2.0 * Qdx)).sum()
-        acc["v"][g] += (dm * (-2.0 * Qdy)).sum()
-        acc["conic"][g] += np.array([[(dm * ddx * ddx).sum(), (dm * ddx * ddy).sum()],
-                                     [(dm * ddx * ddy).sum(), (dm * ddy * ddy).sum()]])
+        gl = bl if rules.grad_limit <= 0 else bl & (ranks[idx] < rules.grad_limit)
+        if gl.any():
+            gC = dL_dC[gl]                      # (P', 3)
+            Ti, ai = Tb[gl], alpha[gl]
+            acc["rgb"][g] += (Ti * ai) @ gC
+            dalpha = (gC * (Ti[:, None] * c[None, :] - B[gl] / (1.0 - ai)[:, None])).sum(1)
+            free = ~clamped[gl]
+            if free.any():
+                da = dalpha[free]
+                acc["opacity"][g] += (da * G[gl][free]).sum()
+                dm = da * (-0.5 * ai[free])
+                ddx, ddy = dx[gl][free], dy[gl][free]
+                Q = proj.conic[g]
+                Qdx = Q[0, 0] * ddx + Q[0, 1] * ddy
+                Qdy = Q[1, 0] * ddx + Q[1, 1] * ddy
+                acc["u"][g] += (dm * (-2.0 * Qdx)).sum()
+                acc["v"][g] += (dm * (-2.0 * Qdy)).sum()
+                acc["conic"][g] += np.array([[(dm * ddx * ddx).sum(), (dm * ddx * ddy).sum()],
+                                             [(dm * ddx * ddy).sum(), (dm * ddy * ddy).sum()]])
+        B[bl] += (Tb[bl] * alpha[bl])[:, None] * c[None, :]
     return fwd
 
 
@@ -105,11 +116,16 @@ def project_backward(scene, proj, g2d: dict) -> dict:
     dM = 2.0 * dSigma @ proj.M
     ds = (dM * proj.R).sum(1)                             # sum_i dM_ik R_ik
     dlog_s = ds * proj.s
-    dMq = _dM_dq(proj.qhat, proj.s)
-    dqh = np.stack([(dM * d).sum((1, 2)) for d in dMq], 1)
-    qh = proj.qhat
-    with np.errstate(all="ignore"):
-        dq = (dqh - qh * (qh * dqh).sum(1, keepdims=True)) / proj.qnorm[:, None]
+    if proj.isotropic:
+        # s = exp((l0 + l1 + l2) / 3) on every axis; the quaternion is not used
+        dlog_s = np.repeat(dlog_s.sum(1, keepdims=True) / 3.0, 3, 1)
+        dq = np.zeros((n, 4))
+    else:
+        dMq = _dM_dq(proj.qhat, proj.s)
+        dqh = np.stack([(dM * d).sum((1, 2)) for d in dMq], 1)
+        qh = proj.qhat
+        with np.errstate(all="ignore"):
+            dq = (dqh - qh * (qh * dqh).sum(1, keepdims=True)) / proj.qnorm[:, None]
     o = proj.opacity
     dlogit = g2d["opacity"] * o * (1.0 - o)
     # colour: only unclamped channels pass gradient

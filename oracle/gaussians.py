@@ -172,6 +172,7 @@ class Projection:
     cx: float
     cy: float
     sh_degree: int
+    isotropic: bool = False  # Sigma = s^2 I with s = exp(mean log-scale)
 
 
 def project(scene, cam, rules: Rules = Rules()) -> Projection:
@@ -188,10 +189,16 @@ def project(scene, cam, rules: Rules = Rules()) -> Projection:
     Wd, Hd = cam.width, cam.height
 
     with np.errstate(all="ignore"):
-        finite = np.isfinite(mu).all(1) & np.isfinite(log_s).all(1) & np.isfinite(q).all(1) \
-            & np.isfinite(logit) & np.isfinite(sh).all(axis=(0, 1))
-        # activations (Sec. 5.1): s = exp(log s), o = sigmoid(logit); q normalised (Sec. 4)
-        s = np.exp(log_s)
+        finite = np.isfinite(mu).all(1) & np.isfinite(log_s).all(1) & np.isfinite(logit) \
+            & np.isfinite(sh).all(axis=(0, 1))
+        if rules.isotropic:
+            # one radius on all axes (Sec. 7.3 ablation): no rotation, q unused
+            s = np.repeat(np.exp(log_s.mean(1))[:, None], 3, 1)
+            q = np.tile([1.0, 0.0, 0.0, 0.0], (n, 1))
+        else:
+            finite &= np.isfinite(q).all(1)
+            # activations (Sec. 5.1): s = exp(log s); q normalised (Sec. 4)
+            s = np.exp(log_s)
         o = 1.0 / (1.0 + np.exp(-logit))
         qnorm = np.sqrt((q * q).sum(1))
         ok_q = finite & (qnorm > 0)
@@ -265,4 +272,4 @@ def project(scene, cam, rules: Rules = Rules()) -> Projection:
     return Projection(n, valid, drawable, z32, zkey, u, v, cov2d, conic, i_lo, i_hi, j_lo, j_hi,
                       tx0, tx1, ty0, ty1, o, rgb, rgb_raw, aabb_margin & valid,
                       s, qhat, qnorm, R, M, Sigma, t, J, W, dirs, dist, Y,
-                      Wd, Hd, fx, fy, cx, cy, scene.sh_degree)
+                      Wd, Hd, fx, fy, cx, cy, scene.sh_degree, bool(rules.isotropic))

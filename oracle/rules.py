@@ -11,6 +11,14 @@
 * Skip any alpha below 1/255, clamp alpha to at most 0.99, and stop a pixel
   before its accumulated opacity would exceed 0.9999, i.e. when T(1 - alpha)
   would fall below 1e-4 (App. C, "Numerical stability").
+
+Two switches reproduce the ablations of Sec. 7.3 (both off in the method itself):
+* isotropic: one scalar radius per Gaussian on all three axes, Sigma = s^2 I. The
+  scalar is s = exp of the mean of the three stored log-scales (so three equal
+  rows behave exactly as one parameter, each receiving a third of its gradient);
+  the quaternion is not used and receives no gradient.
+* grad_limit = N > 0: only the N front-most Gaussians blended at a pixel receive
+  gradient from it (their gradient is the exact one); the image is unchanged.
 """
 from __future__ import annotations
 
@@ -26,6 +34,8 @@ class Rules:
     alpha_max: float = 0.99
     T_min: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
+    isotropic: bool = False
+    grad_limit: int = 0
     # Decision margins: a pixel is "ambiguous" when one of its threshold decisions
     # lies so close to the threshold that an FP32 evaluation may legitimately take
     # the other branch. Each width is about 10x an FP32 error bound of the quantity:
