@@ -93,6 +93,12 @@ typedef struct gs_config {
   int32_t sort_digit_bits; /* radix digit width of gs_sort: 4..8, default 8 */
   int32_t lds_batch;       /* list entries each wave stages in LDS per round: 64 or 128
                               (0 = 64); changes speed only */
+  /* Ablation switches of Sec. 7.3 (0 in the method itself): */
+  int32_t isotropic;       /* 1: one radius on all axes, Sigma = s^2 I with s = exp of the
+                              mean of the three log-scales; quaternions unused, zero
+                              gradient, each log-scale row gets a third of the gradient */
+  int32_t grad_limit;      /* N > 0: a pixel passes gradient only to its N front-most
+                              blended Gaussians (image unchanged); 0: to all of them */
 } gs_config;
 
 typedef struct gs_params {

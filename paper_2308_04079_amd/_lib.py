@@ -36,7 +36,8 @@ class GsConfig(ctypes.Structure):
                 ("near_z", ctypes.c_float), ("sigma_extent", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("sort_digit_bits", ctypes.c_int32), ("lds_batch", ctypes.c_int32)]
+                ("sort_digit_bits", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
+                ("isotropic", ctypes.c_int32), ("grad_limit", ctypes.c_int32)]
 
 
 class GsParams(ctypes.Structure):

@@ -16,6 +16,8 @@ int check_config(const gs_config* cfg) {
   if (!(cfg->T_min > 0.0f) || !(cfg->T_min < 1.0f)) return GS_ERR_ARG;
   if (cfg->sort_digit_bits < 4 || cfg->sort_digit_bits > 8) return GS_ERR_ARG;
   if (cfg->lds_batch != 0 && cfg->lds_batch != 64 && cfg->lds_batch != 128) return GS_ERR_ARG;
+  if (cfg->isotropic != 0 && cfg->isotropic != 1) return GS_ERR_ARG;
+  if (cfg->grad_limit < 0) return GS_ERR_ARG;
   for (int c = 0; c < 3; ++c)
     if (!isfinite(cfg->bg[c])) return GS_ERR_ARG;
   return GS_OK;
@@ -32,6 +34,8 @@ Rules make_rules(const gs_config* cfg) {
   r.bg[0] = cfg->bg[0];
   r.bg[1] = cfg->bg[1];
   r.bg[2] = cfg->bg[2];
+  r.isotropic = cfg->isotropic;
+  r.grad_limit = cfg->grad_limit;
   return r;
 }
 

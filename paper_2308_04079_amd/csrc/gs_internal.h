@@ -40,6 +40,8 @@ struct TileViews {
 struct Rules {
   float near_z, ext, ext2, alpha_min, alpha_max, T_min;
   float bg[3];
+  int32_t isotropic;   // Sigma = s^2 I, s = exp(mean log-scale)
+  int32_t grad_limit;  // > 0: only the N front-most blended Gaussians get gradients
 };
 
 static_assert(sizeof(ProjViews) < 3000, "kernel argument block too large");

@@ -32,22 +32,33 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
   const float ls0 = log_scales[g], ls1 = log_scales[n + g], ls2 = log_scales[2 * n + g];
   const float q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
   const float lg = logits[g];
+  const bool iso = rules.isotropic != 0;
   bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ls0) && isfinite(ls1) &&
-                isfinite(ls2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) &&
-                isfinite(lg);
+                isfinite(ls2) && isfinite(lg);
+  if (!iso) finite = finite && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3);
   float shc[K][3];
   load_sh<K>(sh, n, g, shc);
 #pragma unroll
   for (int k = 0; k < K; ++k) finite = finite && isfinite(shc[k][0] + shc[k][1] + shc[k][2]);
-  const double qn = sqrt((double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3);
+  const double qn = iso ? 1.0 : sqrt((double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3);
   const bool alive = finite && qn > 0.0;
   double M[9];
   double opac = 0.0;
   if (alive) {
     double R[9];
-    const double iq = 1.0 / qn;
-    quat_to_rot(q0 * iq, q1 * iq, q2 * iq, q3 * iq, R);
-    const double s0 = exp((double)ls0), s1 = exp((double)ls1), s2 = exp((double)ls2);
+    double s0, s1, s2;
+    if (iso) {
+      // one radius on all axes (Sec. 7.3 ablation): Sigma = s^2 I, no rotation
+      R[0] = R[4] = R[8] = 1.0;
+      R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.0;
+      s0 = s1 = s2 = exp((((double)ls0 + (double)ls1) + (double)ls2) / 3.0);
+    } else {
+      const double iq = 1.0 / qn;
+      quat_to_rot(q0 * iq, q1 * iq, q2 * iq, q3 * iq, R);
+      s0 = exp((double)ls0);
+      s1 = exp((double)ls1);
+      s2 = exp((double)ls2);
+    }
     for (int r = 0; r < 3; ++r) {
       M[r * 3 + 0] = R[r * 3 + 0] * s0;
       M[r * 3 + 1] = R[r * 3 + 1] * s1;
@@ -113,15 +124,28 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   {
   double dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0};
   double dop = 0.0, opac = 0.0;
+  const bool iso = rules.isotropic != 0;
   if (any) {
-    const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
-    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3), iq = 1.0 / qn;
-    const double qh[4] = {q0 * iq, q1 * iq, q2 * iq, q3 * iq};
+    double qh[4] = {1.0, 0.0, 0.0, 0.0}, iq = 1.0;
     double R[9], M[9];
-    quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
-    s[0] = exp((double)log_scales[g]);
-    s[1] = exp((double)log_scales[n + g]);
-    s[2] = exp((double)log_scales[2 * n + g]);
+    if (iso) {
+      R[0] = R[4] = R[8] = 1.0;
+      R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.0;
+      s[0] = s[1] = s[2] = exp((((double)log_scales[g] + (double)log_scales[n + g]) +
+                               (double)log_scales[2 * n + g]) / 3.0);
+    } else {
+      const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
+      const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+      iq = 1.0 / qn;
+      qh[0] = q0 * iq;
+      qh[1] = q1 * iq;
+      qh[2] = q2 * iq;
+      qh[3] = q3 * iq;
+      quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
+      s[0] = exp((double)log_scales[g]);
+      s[1] = exp((double)log_scales[n + g]);
+      s[2] = exp((double)log_scales[2 * n + g]);
+    }
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * s[c];
     opac = 1.0 / (1.0 + exp(-(double)logits[g]));
@@ -197,7 +221,12 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
     dqh[3] = 2.0 * (-2.0 * k * dR[0] - r * dR[1] + i * dR[2] + r * dR[3] - 2.0 * k * dR[4] +
                     j * dR[5] + i * dR[6] + j * dR[7]);
     const double dotq = qh[0] * dqh[0] + qh[1] * dqh[1] + qh[2] * dqh[2] + qh[3] * dqh[3];
-    for (int c = 0; c < 4; ++c) dq[c] = (dqh[c] - qh[c] * dotq) * iq;
+    for (int c = 0; c < 4; ++c) dq[c] = iso ? 0.0 : (dqh[c] - qh[c] * dotq) * iq;
+    if (iso) {
+      // s = exp((l0 + l1 + l2) / 3): every row receives a third of dL/dlog s
+      const double third = (ds[0] * s[0] + ds[1] * s[1] + ds[2] * s[2]) / 3.0;
+      ds[0] = ds[1] = ds[2] = third / s[0];
+    }
   }
   // the geometry gradients are final here; only the mean still gains the SH term
   d_log_scales[g] = (float)(ds[0] * s[0]);

@@ -215,8 +215,8 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
     img[p] = fmaf(T, rules.bg[0], C0);
     img[HW + p] = fmaf(T, rules.bg[1], C1);
     img[2 * HW + p] = fmaf(T, rules.bg[2], C2);
-    T_final[P + p] = T;
-    last_idx[P + p] = last;
+    if (T_final) T_final[P + p] = T;      // both NULL on the forward-only path
+    if (last_idx) last_idx[P + p] = last;
   }
 }
 
@@ -264,7 +264,7 @@ __device__ __forceinline__ float wave_reduce9_scatter(float a0, float a1, float 
   return v;
 }
 
-template <int TS, int R>
+template <int TS, int R, bool LIMIT>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
@@ -302,6 +302,23 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   if (wave_last < (int)start) return;  // no pixel of this wave blended anything
   const bool atomic_lane = lane < 16 && ((kReduceLanes >> lane) & 1u);
   const int atomic_slot = reduce_index((uint32_t)lane);
+  // limited-gradient ablation: count the pixel's blended Gaussians first, so the
+  // back-to-front walk knows each one's front-to-back rank
+  int n_blended = 0, from_back = 0;
+  if constexpr (LIMIT) {
+    for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
+      const int64_t bot = max((int64_t)start, top - (BATCH - 1));
+      const int cnt = stage_batch<R>(record, vals, bot, top, w, rules.ext, s_geo[wave],
+                                     s_shape[wave], s_col[wave], s_gid[wave]);
+      for (int k = cnt - 1; k >= 0; --k) {
+        const int32_t pos = (int32_t)__float_as_uint(s_col[wave][k].w);
+        Eval e;
+        eval_alpha(s_geo[wave][k], s_shape[wave][k], fpx, fpy, rules, e);
+        n_blended += ((pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min)) ? 1 : 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
   for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
     const int64_t bot = max((int64_t)start, top - (BATCH - 1));
     const int cnt = stage_batch<R>(record, vals, bot, top, w, rules.ext, s_geo[wave],
@@ -315,15 +332,21 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       eval_alpha(geo, shape, fpx, fpy, rules, e);
       // branch-free: non-contributing lanes add zeros and keep their state
       const bool contrib = (pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min);
+      bool grad_on = contrib;
+      if constexpr (LIMIT) {
+        grad_on = contrib && (n_blended - 1 - from_back) < rules.grad_limit;
+        from_back += contrib ? 1 : 0;
+      }
       const float inv = contrib ? __builtin_amdgcn_rcpf(1.0f - e.alpha) : 1.0f;
       T = T * inv;  // transmittance in front of this Gaussian
       const float wgt = contrib ? T * e.alpha : 0.0f;
-      const float d_r = wgt * g0, d_g = wgt * g1, d_b = wgt * g2;
+      const float gwgt = grad_on ? wgt : 0.0f;
+      const float d_r = gwgt * g0, d_g = gwgt * g1, d_b = gwgt * g2;
       const float gc = fmaf(g2, col.z, fmaf(g1, col.y, g0 * col.x));
       float dalpha = fmaf(T, gc, -S * inv);
       S = fmaf(wgt, gc, S);
       // alpha = min(alpha_max, o G): no gradient through a clamped alpha
-      dalpha = (contrib && shape.w * e.G <= rules.alpha_max) ? dalpha : 0.0f;
+      dalpha = (grad_on && shape.w * e.G <= rules.alpha_max) ? dalpha : 0.0f;
       const float d_o = dalpha * e.G;
       // dalpha/dm = -alpha / 2; m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = pixel - mean
       const float q = -dalpha * e.alpha;
@@ -331,7 +354,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       const float d_mx = -fmaf(t0, shape.x, t1 * shape.y);
       const float d_my = -(t1 * shape.z);
       const float d_w00 = t0 * e.dx, d_w10 = t1 * e.dx, d_w11 = t1 * e.dy;
-      if (__ballot(contrib) != 0ull) {
+      if (__ballot(grad_on) != 0ull) {
         const float tot = wave_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g,
                                                d_b);
         if (atomic_lane)
@@ -397,7 +420,7 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
   TileViews tv;
   int rc = render_common(proj, inst, tile_ranges, cams, n_views, cfg, n, &tv);
   if (rc != GS_OK) return rc;
-  if (!image || !T_final || !last_idx) return GS_ERR_ARG;
+  if (!image || (!T_final) != (!last_idx)) return GS_ERR_ARG;
   const Rules rules = make_rules(cfg);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
@@ -444,9 +467,23 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
 #define GS_BWD(TS, R)                                                                          \
-  render_bwd_kernel<TS, R><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                      \
+  render_bwd_kernel<TS, R, false><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(               \
       proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
       dL_dimage, grad2d)
+#define GS_BWD_LIMITED(TS)                                                                     \
+  render_bwd_kernel<TS, 1, true><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                \
+      proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
+      dL_dimage, grad2d)
+  if (cfg->grad_limit > 0) {
+    // the ablation path stages 64 entries per round whatever lds_batch says
+    switch (cfg->tile_size) {
+      case 8: GS_BWD_LIMITED(8); break;
+      case 32: GS_BWD_LIMITED(32); break;
+      default: GS_BWD_LIMITED(16); break;
+    }
+    return launch_status();
+  }
+#undef GS_BWD_LIMITED
   const bool two = cfg->lds_batch == 128;
   switch (cfg->tile_size) {
     case 8: if (two) GS_BWD(8, 2); else GS_BWD(8, 1); break;

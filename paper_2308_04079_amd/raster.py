@@ -106,19 +106,25 @@ class Rasterizer:
     """Forward and backward of the tile rasterizer over V >= 1 views per call.
 
     capacity: instance capacity (grows automatically when ``check`` is on).
+    isotropic, grad_limit: the ablation switches of Sec. 7.3 (see gs_config).
     """
 
     def __init__(self, sh_degree: int = 3, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
                  capacity: int | None = None, growth: float = 1.25, sort_digit_bits: int = 8,
-                 lds_batch: int = 64):
+                 lds_batch: int = 64, isotropic: bool = False, grad_limit: int = 0):
         self.cfg = _lib.default_config(sh_degree=sh_degree, tile_size=tile_size, bg=bg,
-                                       sort_digit_bits=sort_digit_bits, lds_batch=lds_batch)
+                                       sort_digit_bits=sort_digit_bits, lds_batch=lds_batch,
+                                       isotropic=int(bool(isotropic)), grad_limit=int(grad_limit))
         self.capacity = capacity
         self.growth = growth
         self.check = True   # RasterizeFunction: read the status word after each forward
 
     # -- forward -----------------------------------------------------------------
-    def render(self, params: GaussianParams, cams, check: bool = True) -> RenderState:
+    def render(self, params: GaussianParams, cams, check: bool = True,
+               for_backward: bool = True) -> RenderState:
+        """Project, bin, sort and blend all views. ``for_backward=False`` is the
+        forward-only path: no per-pixel backward state is written (T_final and
+        last_idx of the result are empty)."""
         lib = _lib.lib()
         if params.sh_degree != self.cfg.sh_degree:
             raise ValueError(f"params carry SH degree {params.sh_degree}, config has "
@@ -148,8 +154,9 @@ class Rasterizer:
         ranges = torch.empty(2 * n_tiles, dtype=torch.int32, device=dev)
         order = torch.empty(n_tiles, dtype=torch.int32, device=dev)
         image = torch.empty(3 * pix[-1], dtype=torch.float32, device=dev)
-        T_final = torch.empty(pix[-1], dtype=torch.float32, device=dev)
-        last_idx = torch.empty(pix[-1], dtype=torch.int32, device=dev)
+        npix = pix[-1] if for_backward else 0
+        T_final = torch.empty(npix, dtype=torch.float32, device=dev)
+        last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
         bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n)), dtype=torch.uint8,
                              device=dev)
         while True:
@@ -174,7 +181,8 @@ class Rasterizer:
                                               sort_ws.numel(), stream))
             _lib.check("gs_render_fwd", lib.gs_render_fwd(
                 ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(ranges), _lib.ptr(order), cams_c,
-                V, cfg, _lib.ptr(image), _lib.ptr(T_final), _lib.ptr(last_idx), n, stream))
+                V, cfg, _lib.ptr(image), _lib.ptr(T_final) if for_backward else 0,
+                _lib.ptr(last_idx) if for_backward else 0, n, stream))
             if not check:
                 break
             st, ct = state.read_status()
@@ -197,6 +205,8 @@ class Rasterizer:
         stream = torch.cuda.current_stream(dev).cuda_stream
         cfg = ctypes.byref(self.cfg)
         V, n = state.n_views, state.n
+        if state.T_final.numel() == 0:
+            raise ValueError("the state was rendered with for_backward=False")
         if dL_dimage.numel() != state.image.numel() or dL_dimage.dtype != torch.float32:
             raise ValueError("dL_dimage must match the flat float32 image layout")
         dL_dimage = dL_dimage.contiguous()

@@ -43,7 +43,7 @@ def test_binding_covers_only_declared_symbols(L):
 
 def test_struct_sizes_match_the_header_layout(L):
     assert ctypes.sizeof(L.GsCamera) == 4 * 18
-    assert ctypes.sizeof(L.GsConfig) == 4 * 12
+    assert ctypes.sizeof(L.GsConfig) == 4 * 14
     assert ctypes.sizeof(L.GsParams) == 8 * 6
     assert ctypes.sizeof(L.GsInstances) == 8 * 7
 
@@ -54,6 +54,7 @@ def test_default_config_is_the_papers_rules(L):
     assert abs(c.near_z - 0.2) < 1e-7 and c.sigma_extent == 3.0
     assert abs(c.alpha_min - 1 / 255) < 1e-9 and abs(c.alpha_max - 0.99) < 1e-7
     assert abs(c.T_min - 1e-4) < 1e-10 and list(c.bg) == [0.0, 0.0, 0.0]
+    assert (c.isotropic, c.grad_limit) == (0, 0)   # the method, not its ablations
 
 
 def test_tile_layout_and_key_bits(L):
@@ -76,6 +77,10 @@ def test_host_argument_checks_return_before_any_launch(L):
     cc = L.make_cameras([scenes.pinhole_camera(64, 64)])
     cfg = L.default_config()
     bad = L.default_config(sh_degree=5)
+    for k, v in (("isotropic", 2), ("grad_limit", -1), ("lds_batch", 96), ("tile_size", 12)):
+        b = L.default_config(**{k: v})
+        assert lib.gs_project(ctypes.byref(L.GsParams(0, 0, 0, 0, 0, 10)), cc, 1, ctypes.byref(b),
+                              ctypes.byref(L.GsProjected(0, 0, 0)), None) == L.ERR_ARG, k
     p = L.GsParams(0, 0, 0, 0, 0, 10)
     proj = L.GsProjected(0, 0, 0)
     assert lib.gs_project(ctypes.byref(p), cc, 1, ctypes.byref(bad), ctypes.byref(proj), None) == L.ERR_ARG
