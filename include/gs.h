@@ -313,6 +313,21 @@ int gs_densify_apply(const gs_params* params, int32_t sh_degree, const uint8_t* 
  * applied to the logits in place. */
 int gs_reset_opacity(float* opacity_logits, int64_t n, float max_opacity, gs_stream_t stream);
 
+/* Carry per-Gaussian state laid out like gs_params (e.g. the optimiser's moments)
+ * through the densification planned by gs_densify_plan: output j of a Gaussian g
+ * takes state[g], or zeros when zero_created != 0 and g was cloned or split.
+ * out is sized like gs_densify_apply's output (n_out Gaussians). */
+int gs_densify_gather(const gs_params* state, int32_t sh_degree, const uint8_t* action,
+                      const uint32_t* offsets, int32_t zero_created, const gs_params_grad* out,
+                      int64_t n_out, gs_stream_t stream);
+
+/* One Adam step (the optimiser of Alg. 1; Kingma and Ba) over n values, in place:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t >= 1 the step count.
+ * All four are device arrays of n floats (float4 accesses when all are 16-byte aligned). */
+int gs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int32_t t, gs_stream_t stream);
+
 /* Copy the device status word to the host after synchronising `stream`
  * (the only synchronising call; not for use under graph capture). */
 int gs_read_status(const gs_instances* inst, uint32_t* status, uint32_t* count,

@@ -119,6 +119,13 @@ EXPORTS = {
                                         ctypes.c_void_p, ctypes.c_void_p, P(GsDensifyConfig),
                                         P(GsParamsGrad), ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "gs_densify_gather": (ctypes.c_int, [P(GsParams), ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int32, P(GsParamsGrad),
+                                         ctypes.c_int64, ctypes.c_void_p]),
+    "gs_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_int32, ctypes.c_void_p]),
     "gs_reset_opacity": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float,
                                         ctypes.c_void_p]),
     "gs_read_status": (ctypes.c_int, [P(GsInstances), P(ctypes.c_uint32), P(ctypes.c_uint32),

@@ -213,6 +213,38 @@ densify_apply_kernel(gs_params in, const uint8_t* __restrict__ action,
   }
 }
 
+// Per-Gaussian state laid out like the parameters (e.g. optimiser moments) carried
+// through a densification: every output takes its source's values, or zeros for the
+// Gaussians a clone or split created when zero_created is set.
+template <int K>
+__global__ void __launch_bounds__(256)
+densify_gather_kernel(gs_params in, const uint8_t* __restrict__ action,
+                      const uint32_t* __restrict__ offsets, int zero_created, int64_t n_out,
+                      float* __restrict__ o_means, float* __restrict__ o_log_scales,
+                      float* __restrict__ o_quats, float* __restrict__ o_logits,
+                      float* __restrict__ o_sh) {
+  const int64_t n = in.n;
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= n) return;
+  const uint8_t a = action[g];
+  if (a == kRemove) return;
+  const int64_t j0 = offsets[g];
+  const int copies = a == kKeep ? 1 : 2;
+  if (j0 + copies > n_out) return;   // defensive: outputs were sized from the plan
+  const float keep = (a == kKeep || !zero_created) ? 1.0f : 0.0f;
+  for (int c = 0; c < copies; ++c) {
+    const int64_t j = j0 + c;
+    for (int r = 0; r < 3; ++r) {
+      o_means[r * n_out + j] = keep * in.means[r * n + g];
+      o_log_scales[r * n_out + j] = keep * in.log_scales[r * n + g];
+    }
+    for (int r = 0; r < 4; ++r) o_quats[r * n_out + j] = keep * in.quats[r * n + g];
+    o_logits[j] = keep * in.opacity_logits[g];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) o_sh[(int64_t)k * n_out + j] = keep * in.sh[(int64_t)k * n + g];
+  }
+}
+
 __global__ void __launch_bounds__(256)
 reset_opacity_kernel(float* __restrict__ logits, int64_t n, float cap) {
   const int64_t stride = (int64_t)gridDim.x * 256;
@@ -326,6 +358,33 @@ extern "C" int gs_densify_apply(const gs_params* params, int32_t sh_degree, cons
     default: GS_APPLY(16); break;
   }
 #undef GS_APPLY
+  return launch_status();
+}
+
+extern "C" int gs_densify_gather(const gs_params* state, int32_t sh_degree, const uint8_t* action,
+                                 const uint32_t* offsets, int32_t zero_created,
+                                 const gs_params_grad* out, int64_t n_out, gs_stream_t stream) {
+  if (!state || !out || state->n < 0 || n_out < 0) return GS_ERR_ARG;
+  if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
+  const int64_t n = state->n;
+  if (n == 0 || n_out == 0) return GS_OK;
+  if (!state->means || !state->log_scales || !state->quats || !state->opacity_logits ||
+      !state->sh || !action || !offsets || !out->means || !out->log_scales || !out->quats ||
+      !out->opacity_logits || !out->sh)
+    return GS_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)((n + 255) / 256));
+#define GS_GATHER(K)                                                                            \
+  densify_gather_kernel<K><<<grid, 256, 0, s>>>(*state, action, offsets, zero_created, n_out,   \
+                                                out->means, out->log_scales, out->quats,      \
+                                                out->opacity_logits, out->sh)
+  switch (sh_degree) {
+    case 0: GS_GATHER(1); break;
+    case 1: GS_GATHER(4); break;
+    case 2: GS_GATHER(9); break;
+    default: GS_GATHER(16); break;
+  }
+#undef GS_GATHER
   return launch_status();
 }
 

@@ -126,9 +126,10 @@ class Rasterizer:
         forward-only path: no per-pixel backward state is written (T_final and
         last_idx of the result are empty)."""
         lib = _lib.lib()
-        if params.sh_degree != self.cfg.sh_degree:
+        if params.sh_degree < self.cfg.sh_degree:
             raise ValueError(f"params carry SH degree {params.sh_degree}, config has "
                              f"{self.cfg.sh_degree}")
+        # a higher stored degree renders its first (deg + 1)^2 bands (the SH ramp)
         cams = list(cams)
         V = len(cams)
         n = params.n
@@ -220,6 +221,9 @@ class Rasterizer:
             _lib.ptr(grad2d), n, stream))
         grads = {k: torch.empty_like(getattr(params, k))
                  for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+        k_active = (self.cfg.sh_degree + 1) ** 2
+        if grads["sh"].shape[0] > k_active:
+            grads["sh"][k_active:].zero_()      # bands not yet active get no gradient
         gp = _lib.GsParamsGrad(*(_lib.ptr(grads[k]) for k in
                                  ("means", "log_scales", "quats", "opacity_logits", "sh")))
         pr = params.c_struct()
