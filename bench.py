@@ -179,7 +179,7 @@ def main():
         log("[bench] copy probe: 268435456 bytes read, 268435456 bytes written")
         del src, dst
 
-    roof = roofline(stages, state, count, sc.n, V)
+    roof = roofline(stages, state, count, sc.n, V, rast.cfg)
     hbm = hbm_rates(stages["ms"], stages["state"], count, sc.n, V, (sc.sh_degree + 1) ** 2,
                     rast.cfg.sort_digit_bits)
     q = np.percentile(np.array(step_ms), [10, 50, 90])
@@ -283,7 +283,7 @@ def time_stages(rast, params, cams, target, steps, zero_loss):
         proj, inst = st.projected(), st.instances()
         pr = params.c_struct()
         V, n = st.n_views, st.n
-        bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n)), dtype=torch.uint8,
+        bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n, cfg)), dtype=torch.uint8,
                              device="cuda")
         sort_ws = torch.empty(max(1, lib.gs_sort_workspace_bytes(st.capacity, st.n_tiles, cfg)),
                               dtype=torch.uint8, device="cuda")
@@ -350,7 +350,7 @@ def measured_traffic(kernel):
     return rec["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
-def processed_pairs(st, T=16):
+def processed_pairs(st, cfg, T=16):
     """(wave, Gaussian) pairs the blend-backward launch evaluates.
 
     A wave owns an 8x8 pixel block of a tile; it walks the tile's list from the
@@ -363,7 +363,7 @@ def processed_pairs(st, T=16):
     dev = st.ranges.device
     M = int(st.count.item())
     vals = st.vals[:M].long() & 0xFFFFFFFF
-    tile = (st.keys[:M] >> 32).long()
+    tile = st.tile_ids(cfg)[:M].long()
     rec = st.record.view(-1, 12)
     lo = rec[vals, 0].view(torch.int32).long()
     hi = rec[vals, 1].view(torch.int32).long()
@@ -407,7 +407,7 @@ def processed_pairs(st, T=16):
     return total
 
 
-def roofline(stages, state, count, n, V):
+def roofline(stages, state, count, n, V, cfg):
     """Roofline of the dominant kernel. For the blend kernels (VALU bound): lane
     evaluations actually issued (processed pairs x 64) x the arithmetic of one
     evaluation, against the FP32 VALU issue rate."""
@@ -415,7 +415,7 @@ def roofline(stages, state, count, n, V):
     dom = max(("render_fwd", "render_bwd", "project", "project_bwd", "sort"), key=lambda k: ms[k])
     st = stages["state"]
     if dom in ("render_bwd", "render_fwd"):
-        pairs = processed_pairs(st)
+        pairs = processed_pairs(st, cfg)
         ops = BWD_OPS_PER_EVAL if dom == "render_bwd" else FWD_OPS_PER_EVAL
         lane_evals = pairs * 64
         achieved = lane_evals * ops / (ms[dom] * 1e-3) / 1e12
@@ -436,27 +436,28 @@ def hbm_rates(ms, st, count, n, V, K, digit_bits):
     """Algorithmic HBM bytes of the streaming stages and the rate each reaches.
 
     project: parameters once (4 (11 + 3K) B per Gaussian) + depth key and tile count
-    per (view, Gaussian) + a 48 B record per visible one; bin: tile counts read twice
-    (block sums, then expansion) + the box of each visible Gaussian + 12 B per instance
-    written; sort: every pass reads and writes 12 B per instance (the minimum of any
-    sort is one such pass); project_bwd: parameters read and gradients written
+    per (view, Gaussian) + a 48 B record per visible one; bin: tile counts read once,
+    per visible pair its depth key and pixel box read, 16 B moved per depth-sort pass
+    (key and value read and written), 8 B written per instance; sort: 16 B per
+    instance per tile-id pass; project_bwd: parameters read and gradients written
     (2 x 4 (11 + 3K) B per Gaussian), tile counts, and per visible (view, Gaussian) its
     record and its 36 B screen-space gradient.
     """
     from paper_2308_04079_amd import _lib
     vis = int((st.tiles_touched[:V * n] > 0).sum().item())
     par = 4 * (11 + 3 * K)
-    bits = _lib.lib().gs_sort_key_bits(st.n_tiles)
-    passes = -(-bits // digit_bits)
+    tile_passes = -(-_lib.lib().gs_sort_key_bits(st.n_tiles) // digit_bits)
+    depth_passes = -(-31 // digit_bits)
     b = {"project": par * n + 8 * V * n + 48 * vis,
-         "bin": 8 * V * n + 16 * vis + 12 * count,
-         "sort": 24 * count * passes,
+         "bin": 4 * V * n + (12 + 16 * depth_passes) * vis + 8 * count,
+         "sort": 16 * count * tile_passes,
          "project_bwd": 2 * par * n + 4 * V * n + (48 + 36) * vis}
     out = {}
     for k, v in b.items():
         gbs = v / (ms[k] * 1e-3) / 1e9
         out[k] = {"bytes": v, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    out["sort"]["passes"] = passes
+    out["bin"]["depth_passes"] = depth_passes
+    out["sort"]["passes"] = tile_passes
     out["visible_pairs"] = vis
     return out
 

@@ -135,10 +135,13 @@ typedef struct gs_projected {
   float* record;           /* [V*N][GS_RECORD_FLOATS] */
 } gs_projected;
 
-/* Instance arrays (App. C "Sorting"): one (key, value) per Gaussian and overlapped
- * tile. key = (global tile id << 32) | depth_key, value = v * N + g. gs_bin fills
- * them unsorted; gs_sort leaves them sorted in keys/vals, ping-ponging through
- * keys_alt/vals_alt. */
+/* Instance arrays (App. C "Sorting"): one instance per visible (view, Gaussian)
+ * pair and tile it overlaps, value v * N + g. After gs_sort, vals[0..M) lists the
+ * instances in (global tile id, depth, index) order: the order of the paper's
+ * single sort by the key (tile << 32) | depth. The pipeline reaches it with two
+ * stable 32-bit sorts (gs_bin: pairs by depth; gs_sort: instances by tile id) and
+ * uses keys and keys_alt as scratch (each as two uint32 arrays of capacity
+ * entries); gs_sorted_tile_ids locates the sorted tile id of every instance. */
 typedef struct gs_instances {
   uint64_t* keys;       /* [capacity] */
   uint32_t* vals;       /* [capacity] */
@@ -161,8 +164,8 @@ void gs_default_config(gs_config* cfg);
 int64_t gs_tile_layout(const gs_camera* cams, int32_t n_views, int32_t tile_size,
                        int64_t* tile_offset);
 
-/* Bits of the compacted sort key: 31 depth bits (depth > 0 keeps the sign bit 0)
- * plus the bits of the largest global tile id. */
+/* Bits of the tile-id key that gs_sort sorts on (those of the largest global tile
+ * id); gs_bin's depth sort uses 31 bits (depth > 0 keeps the float's sign bit 0). */
 int32_t gs_sort_key_bits(int64_t n_tiles_total);
 
 /* Project (Alg. 2 CullGaussian + ScreenspaceGaussians; Sec. 4 Eq. volume-render;
@@ -173,12 +176,13 @@ int32_t gs_sort_key_bits(int64_t n_tiles_total);
 int gs_project(const gs_params* params, const gs_camera* cams, int32_t n_views,
                const gs_config* cfg, const gs_projected* out, gs_stream_t stream);
 
-/* Workspace bytes of gs_bin for V*N projected Gaussians. */
-size_t gs_bin_workspace_bytes(int64_t n_total);
+/* Workspace bytes of gs_bin for V*N projected Gaussians (0 on a bad config). */
+size_t gs_bin_workspace_bytes(int64_t n_total, const gs_config* cfg);
 
-/* Bin (Alg. 2 CreateTiles + DuplicateWithKeys; App. C "Sorting"): exclusive scan
- * of tiles_touched, then one (key, value) instance per Gaussian and covered tile,
- * in Gaussian order. Writes the instance count to *inst->count; if it exceeds
+/* Bin (Alg. 2 CreateTiles + DuplicateWithKeys; App. C "Sorting"): the visible
+ * (view, Gaussian) pairs, stably sorted by depth (radix, cfg->sort_digit_bits per
+ * pass), then one instance per pair and covered tile in that order (tiles of a pair
+ * row-major). Writes the instance count to *inst->count; if it exceeds
  * inst->capacity, ORs GS_STATUS_CAPACITY into *inst->status and writes nothing
  * past capacity. n is N (per view). */
 int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
@@ -189,15 +193,20 @@ int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n
 size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total, const gs_config* cfg);
 
 /* Sort (Alg. 2 SortByKeys + IdentifyTileRanges; App. C): stable LSD radix sort of
- * the M = min(*count, capacity) instances by key (onesweep: one histogram pass,
- * then one pass per digit with decoupled look-back), then per global tile the
- * range [start, end) of its instances, written to tile_ranges[t][2] (uint32).
- * Ties in (tile, depth) keep Gaussian order. If tile_order (device, [n_tiles_total])
+ * the M = min(*count, capacity) instances of gs_bin by global tile id (onesweep:
+ * one histogram pass, then one pass per digit with decoupled look-back), which
+ * completes the (tile, depth, index) order, then per global tile the range
+ * [start, end) of its instances, written to tile_ranges[t][2] (uint32). If tile_order (device, [n_tiles_total])
  * is not NULL it receives a permutation of the tile ids, longest list first
  * (bucketed by floor(log2(length))), the issue order for the render calls. */
 int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
             uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
             size_t workspace_bytes, gs_stream_t stream);
+
+/* Device address of the sorted global tile id of every instance after gs_sort
+ * (uint32 [M], inside inst->keys or inst->keys_alt), or NULL on bad arguments. */
+const uint32_t* gs_sorted_tile_ids(const gs_instances* inst, int64_t n_tiles_total,
+                                   const gs_config* cfg);
 
 /* Forward blend (Alg. 2 BlendInOrder; Eq. front-to-back; App. C rules): for every
  * pixel of every view, front to back over its tile's instances: skip pixels

@@ -78,7 +78,8 @@ EXPORTS = {
     "gs_sort_key_bits": (ctypes.c_int32, [ctypes.c_int64]),
     "gs_project": (ctypes.c_int, [P(GsParams), P(GsCamera), ctypes.c_int32, P(GsConfig),
                                   P(GsProjected), ctypes.c_void_p]),
-    "gs_bin_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "gs_bin_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, P(GsConfig)]),
+    "gs_sorted_tile_ids": (ctypes.c_void_p, [P(GsInstances), ctypes.c_int64, P(GsConfig)]),
     "gs_bin": (ctypes.c_int, [P(GsProjected), ctypes.c_int64, P(GsCamera), ctypes.c_int32,
                               P(GsConfig), P(GsInstances), ctypes.c_void_p, ctypes.c_size_t,
                               ctypes.c_void_p]),
@@ -146,10 +147,12 @@ def lib():
     """The loaded library; raises if it has not been built (there is no fallback path)."""
     global _LIB
     if _LIB is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+        # GS_LIBRARY: another build of the same library (e.g. to compare two builds)
+        path = os.environ.get("GS_LIBRARY", LIB_PATH)
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
                                "`python -m paper_2308_04079_amd.build` (hipcc, gfx950)")
-        h = ctypes.CDLL(LIB_PATH)
+        h = ctypes.CDLL(path)
         for name, (res, args) in EXPORTS.items():
             f = getattr(h, name)
             f.restype = res

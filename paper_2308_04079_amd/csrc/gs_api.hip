@@ -96,10 +96,6 @@ int fill_tile_views(const gs_camera* cams, int32_t n_views, int32_t tile, TileVi
   return GS_OK;
 }
 
-int sort_passes(int64_t n_tiles_total, int32_t digit_bits) {
-  const int bits = gs_sort_key_bits(n_tiles_total);
-  return (bits + digit_bits - 1) / digit_bits;
-}
 
 }  // namespace gs
 
@@ -130,11 +126,6 @@ extern "C" int64_t gs_tile_layout(const gs_camera* cams, int32_t n_views, int32_
   return tv.tile_offset[n_views];
 }
 
-extern "C" int32_t gs_sort_key_bits(int64_t n_tiles_total) {
-  int tb = 0;
-  while (tb < 40 && ((int64_t)1 << tb) < n_tiles_total) ++tb;
-  return 31 + tb;
-}
 
 extern "C" int gs_read_status(const gs_instances* inst, uint32_t* status, uint32_t* count,
                               gs_stream_t stream) {

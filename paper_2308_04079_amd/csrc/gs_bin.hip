@@ -1,9 +1,16 @@
-// gs_bin: exclusive scan of tiles_touched over all (view, Gaussian) pairs and one
-// (key, value) instance per covered tile (Alg. 2 CreateTiles + DuplicateWithKeys;
-// App. C "Sorting"). Three launches: per-block sums, a one-block scan of those
-// sums (which also writes the instance count and the capacity check), and a
-// block-local scan fused with the scatter of the instances, so the per-Gaussian
-// offsets never go to memory.
+// gs_bin: one (tile, value) instance per tile a visible (view, Gaussian) pair
+// overlaps (Alg. 2 CreateTiles + DuplicateWithKeys; App. C "Sorting"), emitted in
+// front-to-back order, so that gs_sort only has to sort the instances by tile:
+//   1. compact the visible pairs (index order) with their depth keys;
+//   2. stable radix sort of (depth, index) (31 key bits: depth > 0);
+//   3. exclusive scan of the tile counts in depth order (the instance count and the
+//      capacity check come from an exact sum in step 1);
+//   4. expansion of every pair into its tiles, row-major, writing the global tile id
+//      and the pair's index, partitioned by output instance so every block does
+//      the same work (the nearest pairs cover the most tiles and sort first).
+// The result is the paper's per-instance (tile | depth) key order once sorted by tile.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -11,6 +18,10 @@ namespace gs {
 constexpr int kBinBlock = 256;
 constexpr int kBinItems = 16;                       // per thread
 constexpr int kBinTile = kBinBlock * kBinItems;     // 4096 per block
+// misc words: [0] visible pairs, [1] the same clamped to the capacity, [2..3] the
+// instance count summed over all pairs (64-bit), exact even when the capacity is short,
+// [4] the instances of the (clamped) depth-sorted pairs
+constexpr int kMiscWords = 16;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   const uint32_t lane = __lane_id();
@@ -41,26 +52,63 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* smem4,
   return base + incl - x;
 }
 
+// Item i of the block's range: VISIBLE counts visible pairs (index order); otherwise
+// the tile count of the i-th pair in depth order.
+template <bool VISIBLE>
+__device__ __forceinline__ uint32_t item_value(const int32_t* __restrict__ touched,
+                                               const uint32_t* __restrict__ sorted, int64_t i,
+                                               int64_t n_items) {
+  if (i >= n_items) return 0u;
+  if (VISIBLE) return touched[i] > 0 ? 1u : 0u;
+  return (uint32_t)max(touched[sorted[i]], 0);
+}
+
+__global__ void __launch_bounds__(64)
+bin_init(uint32_t* __restrict__ misc) {
+  if (threadIdx.x < kMiscWords) misc[threadIdx.x] = 0u;
+}
+
+// VISIBLE: per block the number of visible pairs, and the block's instance count
+// added to the 64-bit total at instances_total. Otherwise per block the instance
+// count of the depth-sorted pairs, each pair's count also written densely in depth
+// order to sorted_counts.
+template <bool VISIBLE>
 __global__ void __launch_bounds__(kBinBlock)
-bin_block_sums(const int32_t* __restrict__ touched, int64_t total_items, uint32_t* __restrict__ sums) {
+bin_block_sums(const int32_t* __restrict__ touched, const uint32_t* __restrict__ sorted,
+               int64_t max_items,
+               const uint32_t* __restrict__ n_items_dev, uint32_t* __restrict__ sums,
+               unsigned long long* __restrict__ instances_total,
+               uint32_t* __restrict__ sorted_counts) {
   __shared__ uint32_t s4[kBinBlock / kWave];
+  const int64_t n_items = n_items_dev ? min((int64_t)n_items_dev[0], max_items) : max_items;
   const int64_t base = (int64_t)blockIdx.x * kBinTile;
-  uint32_t acc = 0;
+  uint32_t acc = 0, tiles = 0;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
     const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-    if (i < total_items) acc += (uint32_t)max(touched[i], 0);
+    const uint32_t c = item_value<VISIBLE>(touched, sorted, i, n_items);
+    acc += c;
+    if (VISIBLE && i < n_items) tiles += (uint32_t)max(touched[i], 0);
+    if (!VISIBLE && i < n_items) sorted_counts[i] = c;
   }
   uint32_t tot;
   block_excl_scan(acc, s4, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+  if (VISIBLE) {
+    block_excl_scan(tiles, s4, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(instances_total, (unsigned long long)tot);
+  }
 }
 
-// One block: exclusive scan of the block sums in place; writes the instance
-// count and flags overflow of the capacity.
+// One block: exclusive scan of the block sums in place. Writes the total (and,
+// if clamped is given, the total clamped to `capacity`). With `exact` given, the
+// count written and checked against the capacity is *exact instead (the status
+// flag is raised when it exceeds the capacity).
 __global__ void __launch_bounds__(1024)
 bin_scan_sums(uint32_t* __restrict__ sums, int64_t n_blocks, int64_t capacity,
-              uint32_t* __restrict__ count, uint32_t* __restrict__ status) {
+              uint32_t* __restrict__ total_out, uint32_t* __restrict__ clamped,
+              const unsigned long long* __restrict__ exact, uint32_t* __restrict__ status,
+              uint32_t* __restrict__ own_total) {
   __shared__ uint64_t part[1024];
   const int t = threadIdx.x;
   const int64_t per = (n_blocks + 1023) / 1024;
@@ -82,80 +130,179 @@ bin_scan_sums(uint32_t* __restrict__ sums, int64_t n_blocks, int64_t capacity,
     run += s;
   }
   if (t == 1023) {
-    const uint64_t total = part[1023];
-    count[0] = (uint32_t)min(total, (uint64_t)0xFFFFFFFFu);
-    if (total > (uint64_t)capacity) atomicOr(status, GS_STATUS_CAPACITY);
+    const uint64_t total = exact ? (uint64_t)exact[0] : part[1023];
+    total_out[0] = (uint32_t)min(total, (uint64_t)0xFFFFFFFFu);
+    if (clamped) clamped[0] = (uint32_t)min(total, (uint64_t)capacity);
+    if (status && total > (uint64_t)capacity) atomicOr(status, GS_STATUS_CAPACITY);
+    if (own_total) own_total[0] = (uint32_t)min(part[1023], (uint64_t)0xFFFFFFFFu);
   }
 }
 
-// Load-balanced expansion: the block's 4096 counts are scanned in LDS, then each
-// thread produces output instances o = tid, tid + 256, ... of the block's range,
-// finding its Gaussian by binary search over the LDS prefix sums. Writes are
-// contiguous across the block.
+// The visible pairs of each 4096-block in index order, as (depth key, index) for
+// the sort. Sixteen rounds of 256 consecutive items; within a round a wave ballot
+// and the per-wave totals give every visible item its position, so reads and
+// writes stay contiguous.
 __global__ void __launch_bounds__(kBinBlock)
-bin_duplicate(const int32_t* __restrict__ touched, const uint32_t* __restrict__ depth_key,
-              const float* __restrict__ record, int64_t n, int64_t total_items, TileViews tv,
-              const uint32_t* __restrict__ block_offsets, int64_t capacity,
-              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ uint32_t s_off[kBinTile + 1];
-  __shared__ uint32_t s4[kBinBlock / kWave];
+bin_compact(const int32_t* __restrict__ touched, const uint32_t* __restrict__ depth_key,
+            int64_t total_items, const uint32_t* __restrict__ block_offsets, int64_t capacity,
+            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_wave[kBinItems][kBinBlock / kWave];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int64_t base = (int64_t)blockIdx.x * kBinTile;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  bool vis[kBinItems];
 #pragma unroll
-  for (int j = 0; j < kBinItems; ++j) {
-    const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-    s_off[j * kBinBlock + threadIdx.x] = (i < total_items) ? (uint32_t)max(touched[i], 0) : 0u;
+  for (int r = 0; r < kBinItems; ++r) {
+    const int64_t i = base + (int64_t)r * kBinBlock + threadIdx.x;
+    vis[r] = i < total_items && touched[i] > 0;
+    const uint64_t m = __ballot(vis[r]);
+    if (lane == 0) s_wave[r][wave] = (uint32_t)__popcll(m);
   }
   __syncthreads();
-  // thread t scans the 16 consecutive counts [16 t, 16 t + 16)
-  uint32_t c[kBinItems], local = 0;
+  uint32_t run = block_offsets[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    uint32_t before = 0, round = 0;
+#pragma unroll
+    for (int w = 0; w < kBinBlock / kWave; ++w) {
+      const uint32_t c = s_wave[r][w];
+      before += (w < wave) ? c : 0u;
+      round += c;
+    }
+    const uint64_t m = __ballot(vis[r]);
+    const uint32_t pos = run + before + (uint32_t)__popcll(m & below);
+    if (vis[r] && (int64_t)pos < capacity) {
+      const int64_t i = base + (int64_t)r * kBinBlock + threadIdx.x;
+      keys[pos] = depth_key[i];
+      vals[pos] = (uint32_t)i;
+    }
+    run += round;
+  }
+}
+
+// Start offset of every depth-sorted pair's instances: the block-local scan of the
+// tile counts plus the block's offset.
+__global__ void __launch_bounds__(kBinBlock)
+bin_pair_offsets(const uint32_t* __restrict__ sorted_counts,
+                 const uint32_t* __restrict__ n_sorted_dev, int64_t max_items,
+                 const uint32_t* __restrict__ block_offsets, uint32_t* __restrict__ offs) {
+  __shared__ uint32_t s4[kBinBlock / kWave];
+  const int64_t n_sorted = min((int64_t)n_sorted_dev[0], max_items);
+  const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
+  if ((int64_t)blockIdx.x * kBinTile >= n_sorted) return;   // uniform over the block
+  uint32_t cnt[kBinItems], local = 0;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    c[j] = s_off[threadIdx.x * kBinItems + j];
-    local += c[j];
+    const int64_t s = base + j;
+    cnt[j] = s < n_sorted ? sorted_counts[s] : 0u;
+    local += cnt[j];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan(local, s4, &tot);
+  uint32_t run = block_offsets[blockIdx.x] + block_excl_scan(local, s4, &tot);
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    s_off[threadIdx.x * kBinItems + j] = run;
-    run += c[j];
+    if (base + j < n_sorted) offs[base + j] = run;
+    run += cnt[j];
   }
-  if (threadIdx.x == 0) s_off[kBinTile] = tot;
+}
+
+// Expansion partitioned by output: block b writes instances [4096 b, 4096 b + 4096).
+// Its first pair is found by one binary search over the pair offsets; the (at most
+// 4097) pairs its range can touch are staged in LDS, and each output finds its pair
+// by binary search there. Every block does the same amount of work whatever the
+// tile counts (the nearest Gaussians cover the most tiles and sort first).
+__global__ void __launch_bounds__(kBinBlock)
+bin_expand(const uint32_t* __restrict__ sorted, const uint32_t* __restrict__ n_sorted_dev,
+           int64_t max_items, const float* __restrict__ record, int64_t n, TileViews tv,
+           const uint32_t* __restrict__ offs, const uint32_t* __restrict__ n_out_dev,
+           int64_t capacity, uint32_t* __restrict__ tiles, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_off[kBinTile + 1];
+  __shared__ uint32_t s_slot[kBinTile + 1];
+  __shared__ int64_t s_first;
+  const int64_t n_sorted = min((int64_t)n_sorted_dev[0], max_items);
+  const int64_t n_out = min((int64_t)n_out_dev[0], capacity);
+  const int64_t o0 = (int64_t)blockIdx.x * kBinTile;
+  if (o0 >= n_out) return;   // uniform over the block
+  if (threadIdx.x == 0) {
+    // largest p with offs[p] <= o0 (offsets strictly increase: every pair has a tile)
+    int64_t lo = 0, hi = n_sorted - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)offs[mid] <= o0) lo = mid; else hi = mid - 1;
+    }
+    s_first = lo;
+  }
   __syncthreads();
-  const uint32_t out0 = block_offsets[blockIdx.x];
-  const int T = tv.tile;
-  for (uint32_t o = threadIdx.x; o < tot; o += kBinBlock) {
-    const uint64_t dst = (uint64_t)out0 + o;
-    if (dst >= (uint64_t)capacity) break;   // o only grows
-    // largest j with s_off[j] <= o (counts of zero give equal neighbours: take the last)
-    int lo = 0, hi = kBinTile - 1;
+  const int64_t p0 = s_first;
+  const int n_pairs = (int)min((int64_t)kBinTile + 1, n_sorted - p0);
+  for (int j = threadIdx.x; j < kBinTile + 1; j += kBinBlock) {
+    const bool ok = j < n_pairs;
+    s_off[j] = ok ? offs[p0 + j] : 0xFFFFFFFFu;
+    s_slot[j] = ok ? sorted[p0 + j] : 0u;
+  }
+  __syncthreads();
+  const int64_t o1 = min(o0 + kBinTile, n_out);
+  for (int64_t o = o0 + threadIdx.x; o < o1; o += kBinBlock) {
+    int lo = 0, hi = n_pairs - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= o) lo = mid; else hi = mid - 1;
+      if ((int64_t)s_off[mid] <= o) lo = mid; else hi = mid - 1;
     }
-    const int64_t i = base + lo;
-    const uint32_t k = o - s_off[lo];
-    const int v = (int)(i / n);
-    const int2 lohi = *reinterpret_cast<const int2*>(record + i * GS_RECORD_FLOATS);
-    const int ilo = lohi.x & 0xFFFF, jlo = (lohi.x >> 16) & 0xFFFF;
-    const int ihi = lohi.y & 0xFFFF;
-    const int tx0 = ilo / T, ty0 = jlo / T;
-    const uint32_t wdt = (uint32_t)(ihi / T - tx0 + 1);
-    const uint32_t ty = (uint32_t)ty0 + k / wdt, tx = (uint32_t)tx0 + k % wdt;
-    keys[dst] = ((uint64_t)(uint32_t)(tv.tile_offset[v] + ty * tv.tiles_x[v] + tx) << 32) |
-                (uint64_t)depth_key[i];
-    vals[dst] = (uint32_t)i;
+    const uint32_t i = s_slot[lo];
+    const uint32_t k = (uint32_t)(o - (int64_t)s_off[lo]);
+    int v = 0;
+    while (v + 1 < tv.n_views && (int64_t)i >= (int64_t)(v + 1) * n) ++v;
+    const int2 lohi = *reinterpret_cast<const int2*>(record + (int64_t)i * GS_RECORD_FLOATS);
+    const int T = tv.tile;
+    const uint32_t tx0 = (uint32_t)((lohi.x & 0xFFFF) / T), ty0 = (uint32_t)(((lohi.x >> 16) & 0xFFFF) / T);
+    const uint32_t wdt = (uint32_t)((lohi.y & 0xFFFF) / T) - tx0 + 1;
+    tiles[o] = (uint32_t)tv.tile_offset[v] + (ty0 + k / wdt) * (uint32_t)tv.tiles_x[v] + tx0 + k % wdt;
+    vals[o] = i;
   }
+}
+
+struct BinWs {
+  uint32_t* misc;
+  uint32_t* vis_sums;
+  uint32_t* exp_sums;
+  uint32_t* offs;            // instance offset of every pair in depth order
+  uint32_t* sorted_counts;   // tile count of every pair in depth order
+  void* radix;
+  size_t radix_bytes;
+  int64_t nb;
+};
+
+static size_t align_words(size_t w) { return (w + 63) & ~(size_t)63; }
+
+static size_t bin_ws_layout(int64_t n_total, int db, BinWs* out, void* base) {
+  const int64_t nb = (n_total + kBinTile - 1) / kBinTile;
+  const size_t w_misc = kMiscWords;
+  const size_t w_sums = align_words((size_t)nb + 1);
+  const size_t offs_off = align_words(w_misc + 2 * w_sums);
+  const size_t scounts_off = align_words(offs_off + (size_t)n_total);
+  const size_t radix_off = align_words(scounts_off + (size_t)n_total);
+  const size_t radix_bytes = radix_workspace_bytes(n_total, radix_passes(kDepthKeyBits, db));
+  if (out) {
+    uint32_t* p = static_cast<uint32_t*>(base);
+    out->misc = p;
+    out->vis_sums = p + w_misc;
+    out->exp_sums = p + w_misc + w_sums;
+    out->offs = p + offs_off;
+    out->sorted_counts = p + scounts_off;
+    out->radix = p + radix_off;
+    out->radix_bytes = radix_bytes;
+    out->nb = nb;
+  }
+  return radix_off * sizeof(uint32_t) + radix_bytes;
 }
 
 }  // namespace gs
 
 using namespace gs;
 
-extern "C" size_t gs_bin_workspace_bytes(int64_t n_total) {
-  if (n_total < 0) return 0;
-  const int64_t nb = (n_total + kBinTile - 1) / kBinTile;
-  return (size_t)(nb + 1) * sizeof(uint32_t);
+extern "C" size_t gs_bin_workspace_bytes(int64_t n_total, const gs_config* cfg) {
+  if (n_total < 0 || !cfg || check_config(cfg) != GS_OK) return 0;
+  return bin_ws_layout(n_total, cfg->sort_digit_bits, nullptr, nullptr);
 }
 
 extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n_views,
@@ -173,19 +320,48 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
   if (inst->capacity > GS_MAX_INSTANCES) return GS_ERR_UNSUPPORTED;
   const int64_t total = n * (int64_t)n_views;
   if (total >= ((int64_t)1 << 32)) return GS_ERR_UNSUPPORTED;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int64_t nb = (total + kBinTile - 1) / kBinTile;
   if (total > 0 && (!proj->tiles_touched || !proj->depth_key || !proj->record)) return GS_ERR_ARG;
-  if (workspace_bytes < gs_bin_workspace_bytes(total) || (nb > 0 && !workspace)) return GS_ERR_ARG;
-  uint32_t* sums = static_cast<uint32_t*>(workspace);
-  if (nb > 0)
-    bin_block_sums<<<dim3((unsigned)nb), kBinBlock, 0, s>>>(proj->tiles_touched, total, sums);
-  bin_scan_sums<<<1, 1024, 0, s>>>(sums, nb, inst->capacity, inst->count, inst->status);
-  // the sort ping-pongs between the two buffers and must finish in keys/vals
-  const bool odd = sort_passes(tv.tile_offset[n_views], cfg->sort_digit_bits) & 1;
-  if (nb > 0)
-    bin_duplicate<<<dim3((unsigned)nb), kBinBlock, 0, s>>>(
-        proj->tiles_touched, proj->depth_key, proj->record, n, total, tv, sums, inst->capacity,
-        odd ? inst->keys_alt : inst->keys, odd ? inst->vals_alt : inst->vals);
+  if (!workspace || workspace_bytes < gs_bin_workspace_bytes(total, cfg)) return GS_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  BinWs w;
+  bin_ws_layout(total, cfg->sort_digit_bits, &w, workspace);
+  const int64_t cap = inst->capacity;
+  const int db = cfg->sort_digit_bits;
+  const InstanceBufs b =
+      instance_bufs(inst, radix_passes(tile_key_bits(tv.tile_offset[n_views]), db));
+  unsigned long long* m_total = reinterpret_cast<unsigned long long*>(w.misc + 2);
+  // 1. visible pairs in index order (and the exact instance count)
+  bin_init<<<1, 64, 0, s>>>(w.misc);
+  if (w.nb > 0)
+    bin_block_sums<true><<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(
+        proj->tiles_touched, nullptr, total, nullptr, w.vis_sums, m_total, nullptr);
+  bin_scan_sums<<<1, 1024, 0, s>>>(w.vis_sums, w.nb, cap, w.misc, w.misc + 1, nullptr, nullptr,
+                                   nullptr);
+  if (w.nb > 0)
+    bin_compact<<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(
+        proj->tiles_touched, proj->depth_key, total, w.vis_sums, cap, b.depth.keys[0],
+        b.depth.vals[0]);
+  // 2. by depth (stable: ties keep index order)
+  const int64_t max_vis = std::min(total, cap);
+  rc = radix_sort(b.depth, 0, w.misc + 1, max_vis, kDepthKeyBits, db, w.radix, w.radix_bytes,
+                  inst->status, s);
+  if (rc != GS_OK) return rc;
+  const uint32_t* sorted = b.depth.vals[radix_passes(kDepthKeyBits, db) & 1];
+  // 3. tile counts in depth order -> instance offsets, count and capacity check
+  const int64_t nbe = (max_vis + kBinTile - 1) / kBinTile;
+  if (nbe > 0)
+    bin_block_sums<false><<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(
+        proj->tiles_touched, sorted, max_vis, w.misc + 1, w.exp_sums, nullptr, w.sorted_counts);
+  bin_scan_sums<<<1, 1024, 0, s>>>(w.exp_sums, nbe, cap, inst->count, nullptr, m_total,
+                                   inst->status, w.misc + 4);
+  // 4. the instances, front to back: pair offsets, then an output-partitioned expansion
+  if (nbe > 0)
+    bin_pair_offsets<<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(w.sorted_counts, w.misc + 1,
+                                                              max_vis, w.exp_sums, w.offs);
+  const int64_t nbo = (cap + kBinTile - 1) / kBinTile;
+  if (nbe > 0 && nbo > 0)
+    bin_expand<<<dim3((unsigned)nbo), kBinBlock, 0, s>>>(
+        sorted, w.misc + 1, max_vis, proj->record, n, tv, w.offs, w.misc + 4, cap,
+        b.tiles.keys[0], b.tiles.vals[0]);
   return launch_status();
 }

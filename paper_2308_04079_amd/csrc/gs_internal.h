@@ -52,7 +52,30 @@ int fill_proj_views(const gs_camera* cams, int32_t n_views, int32_t tile, ProjVi
 int fill_tile_views(const gs_camera* cams, int32_t n_views, int32_t tile, TileViews* out);
 int check_config(const gs_config* cfg);
 Rules make_rules(const gs_config* cfg);
-int sort_passes(int64_t n_tiles_total, int32_t digit_bits);
+
+// Radix sort of (key, value) u32 pairs (gs_sort.hip): buffers of the two ping-pong sets.
+struct RadixBufs {
+  uint32_t* keys[2];
+  uint32_t* vals[2];
+};
+// Where the two sorts of the instance pipeline keep their data inside gs_instances:
+// the depth sort of visible pairs uses keys and keys_alt as u32 arrays, the tile sort
+// the first half of each for the tile ids and vals / vals_alt for the values.
+struct InstanceBufs {
+  RadixBufs depth;
+  RadixBufs tiles;             // set 0 is what the expansion writes
+  uint32_t* sorted_tiles;      // tile ids after the tile sort
+};
+int radix_passes(int key_bits, int digit_bits);
+size_t radix_workspace_bytes(int64_t max_items, int passes);
+// Sorts min(*count, max_items) pairs on their low key_bits bits, starting in set
+// `start`; the result is in set (start + passes) & 1. Enqueue only.
+int radix_sort(const RadixBufs& b, int start, const uint32_t* count, int64_t max_items,
+               int key_bits, int digit_bits, void* ws, size_t ws_bytes, uint32_t* status,
+               hipStream_t s);
+int tile_key_bits(int64_t n_tiles_total);
+InstanceBufs instance_bufs(const gs_instances* inst, int tile_passes);
+constexpr int kDepthKeyBits = 31;   // depth > 0: the sign bit of its float word is 0
 
 inline int launch_status() {
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;

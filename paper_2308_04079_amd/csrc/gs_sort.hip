@@ -1,17 +1,19 @@
-// gs_sort: stable LSD radix sort of the instance keys (Alg. 2 SortByKeys; App. C
-// "Sorting"; the paper uses a single GPU radix sort after Merrill and Grimshaw)
-// followed by IdentifyTileRanges.
+// Sorting (Alg. 2 SortByKeys + IdentifyTileRanges; App. C "Sorting"). The paper
+// sorts all instances once by a 64-bit (tile | depth) key. Here the same order is
+// produced by two stable radix sorts of 32-bit keys: gs_bin sorts the visible
+// (view, Gaussian) pairs by depth and expands them into instances in that order;
+// gs_sort then sorts the instances by tile id alone. A stable sort by tile of a
+// sequence already in (depth, index) order is the (tile, depth, index) order, and
+// the instance pass moves 8 bytes per instance over the tile bits only instead of
+// 12 bytes over tile + depth bits.
 //
-// Onesweep structure (Adinets and Merrill, 2022): one histogram pass over the
-// keys computes the digit counts of every pass at once; then each digit pass is a
-// single launch in which a 256-thread block takes 4096 keys in ticket order,
-// ranks them in LDS (wave ballots find the lanes sharing a digit), publishes its
-// digit counts, resolves its global digit offsets by decoupled look-back over the
-// blocks before it, and scatters the keys, staged through LDS so the writes of a
-// digit run are contiguous.
-//
-// The sort key is compacted to (tile id << 31) | depth31: camera depths are
-// positive floats, so bit 31 of the depth word is always 0 and is not sorted on.
+// Each radix sort has the onesweep structure (Adinets and Merrill, 2022): one
+// histogram pass over the keys computes the digit counts of every pass at once; then
+// each digit pass is a single launch in which a 256-thread block takes 4096 keys in
+// ticket order, ranks them in LDS (wave ballots find the lanes sharing a digit),
+// publishes its digit counts, resolves its global digit offsets by decoupled
+// look-back over the blocks before it, and scatters the pairs, staged through LDS so
+// the writes of a digit run are contiguous.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -22,41 +24,49 @@ constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per block
 constexpr int kLookback = 16;                        // predecessors examined per step
-constexpr int kMaxPasses = 16;
+constexpr int kMaxPasses = 8;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ uint64_t compact_key(uint64_t k) {
-  return ((k >> 32) << 31) | (k & 0x7FFFFFFFull);
-}
-
-struct SortWs {
-  uint32_t* hist;      // [passes][256] digit counts, then their exclusive scan
-  uint32_t* ticket;    // [passes]
+struct RadixWs {
+  uint32_t* hist;      // [kMaxPasses][256] digit counts, then their exclusive scan
+  uint32_t* ticket;    // [kMaxPasses]
   uint32_t* lookback;  // [passes][n_blocks][256]
   int64_t n_blocks;
 };
 
-static SortWs carve(void* ws, int64_t capacity) {
-  SortWs w;
+static int64_t radix_blocks(int64_t max_items) {
+  return std::max<int64_t>(1, (max_items + kSortTile - 1) / kSortTile);
+}
+
+size_t radix_workspace_bytes(int64_t max_items, int passes) {
+  return (size_t)(kMaxPasses * 256 + 64 + (int64_t)passes * radix_blocks(max_items) * 256) *
+         sizeof(uint32_t);
+}
+
+static RadixWs carve(void* ws, int64_t max_items) {
+  RadixWs w;
   uint32_t* p = static_cast<uint32_t*>(ws);
-  w.n_blocks = (capacity + kSortTile - 1) / kSortTile;
-  if (w.n_blocks < 1) w.n_blocks = 1;
+  w.n_blocks = radix_blocks(max_items);
   w.hist = p;
   w.ticket = p + kMaxPasses * 256;
   w.lookback = w.ticket + 64;
   return w;
 }
 
+__device__ __forceinline__ int64_t item_count(const uint32_t* count, int64_t max_items) {
+  return min((int64_t)count[0], max_items);
+}
+
 __global__ void __launch_bounds__(256)
-sort_init(SortWs w, int passes, const uint32_t* __restrict__ count, int64_t capacity) {
-  const int64_t M = min((int64_t)count[0], capacity);
+radix_init(RadixWs w, int passes, const uint32_t* __restrict__ count, int64_t max_items) {
+  const int64_t M = item_count(count, max_items);
   const int64_t nb = (M + kSortTile - 1) / kSortTile;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = t0; i < (int64_t)passes * 256; i += stride) w.hist[i] = 0;
+  for (int64_t i = t0; i < (int64_t)kMaxPasses * 256; i += stride) w.hist[i] = 0;
   for (int64_t i = t0; i < 64; i += stride) w.ticket[i] = 0;
   for (int p = 0; p < passes; ++p) {
     uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
@@ -65,16 +75,16 @@ sort_init(SortWs w, int passes, const uint32_t* __restrict__ count, int64_t capa
 }
 
 __global__ void __launch_bounds__(256)
-sort_histogram(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
-               int64_t capacity, int passes, int db, uint32_t* __restrict__ hist) {
+radix_histogram(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count,
+                int64_t max_items, int passes, int db, uint32_t* __restrict__ hist) {
   __shared__ uint32_t sh[kMaxPasses][256];
   for (int i = threadIdx.x; i < kMaxPasses * 256; i += 256) (&sh[0][0])[i] = 0;
   __syncthreads();
-  const int64_t M = min((int64_t)count[0], capacity);
-  const uint64_t mask = (1ull << db) - 1;
+  const int64_t M = item_count(count, max_items);
+  const uint32_t mask = (1u << db) - 1;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
-    const uint64_t ck = compact_key(keys[i]);
-    for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(ck >> (p * db)) & mask], 1u);
+    const uint32_t k = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (p * db)) & mask], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < passes * 256; i += 256) {
@@ -84,7 +94,7 @@ sort_histogram(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ c
 }
 
 __global__ void __launch_bounds__(256)
-sort_scan_hist(uint32_t* __restrict__ hist, int passes) {
+radix_scan_hist(uint32_t* __restrict__ hist, int passes) {
   __shared__ uint32_t s[256];
   const int t = threadIdx.x;
   for (int p = 0; p < passes; ++p) {
@@ -104,15 +114,15 @@ sort_scan_hist(uint32_t* __restrict__ hist, int passes) {
 
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
-sort_pass(const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-          uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-          const uint32_t* __restrict__ count, int64_t capacity, int shift,
-          const uint32_t* __restrict__ digit_start, uint32_t* __restrict__ lookback,
-          uint32_t* __restrict__ ticket, uint32_t* __restrict__ status) {
+radix_pass(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+           uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+           const uint32_t* __restrict__ count, int64_t max_items, int shift,
+           const uint32_t* __restrict__ digit_start, uint32_t* __restrict__ lookback,
+           uint32_t* __restrict__ ticket, uint32_t* __restrict__ status) {
   constexpr int RADIX = 1 << DB;
   constexpr int WAVES = kSortBlock / kWave;
   constexpr int WAVE_ITEMS = kSortTile / WAVES;
-  __shared__ uint64_t s_keys[kSortTile];
+  __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_vals[kSortTile];
   __shared__ uint32_t s_whist[WAVES][RADIX];
   __shared__ uint32_t s_local_base[RADIX];
@@ -125,20 +135,19 @@ sort_pass(const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ val
   for (int i = tid; i < WAVES * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
   __syncthreads();
   const int64_t tile = s_tile;
-  const int64_t M = min((int64_t)count[0], capacity);
+  const int64_t M = item_count(count, max_items);
   if (tile * kSortTile >= M) return;  // uniform over the block
 
   // load: wave w owns the contiguous run [tile*4096 + w*1024, +1024), round r lane l
   const int64_t wbase = tile * kSortTile + (int64_t)wave * WAVE_ITEMS;
-  uint64_t k[kSortItems];
-  uint32_t val[kSortItems], dig[kSortItems], rank[kSortItems];
+  uint32_t k[kSortItems], val[kSortItems], dig[kSortItems], rank[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = wbase + (int64_t)r * kWave + lane;
     const bool valid = i < M;
-    k[r] = valid ? keys_in[i] : ~0ull;
+    k[r] = valid ? keys_in[i] : 0u;
     val[r] = valid ? vals_in[i] : 0u;
-    dig[r] = valid ? (uint32_t)((compact_key(k[r]) >> shift) & (RADIX - 1)) : (uint32_t)RADIX;
+    dig[r] = valid ? ((k[r] >> shift) & (RADIX - 1)) : (uint32_t)RADIX;
   }
   // rank in input order (round-major, then lane): stable
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
@@ -246,32 +255,70 @@ sort_pass(const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ val
   __syncthreads();
   const int n_valid = (int)min((int64_t)kSortTile, M - tile * kSortTile);
   for (int s = tid; s < n_valid; s += kSortBlock) {
-    const uint64_t kk = s_keys[s];
-    const uint32_t d = (uint32_t)((compact_key(kk) >> shift) & (RADIX - 1));
+    const uint32_t kk = s_keys[s];
+    const uint32_t d = (kk >> shift) & (RADIX - 1);
     const uint32_t g = s_global_base[d] + ((uint32_t)s - s_local_base[d]);
     keys_out[g] = kk;
     vals_out[g] = s_vals[s];
   }
 }
 
+int radix_passes(int key_bits, int digit_bits) {
+  return (key_bits + digit_bits - 1) / digit_bits;
+}
+
+int radix_sort(const RadixBufs& b, int start, const uint32_t* count, int64_t max_items,
+               int key_bits, int db, void* ws, size_t ws_bytes, uint32_t* status,
+               hipStream_t s) {
+  const int passes = radix_passes(key_bits, db);
+  if (passes > kMaxPasses) return GS_ERR_UNSUPPORTED;
+  if (passes == 0 || max_items <= 0) return GS_OK;
+  if (ws_bytes < radix_workspace_bytes(max_items, passes)) return GS_ERR_ARG;
+  RadixWs w = carve(ws, max_items);
+  radix_init<<<dim3((unsigned)std::min<int64_t>(w.n_blocks, 1024)), 256, 0, s>>>(
+      w, passes, count, max_items);
+  const int src0 = start & 1;
+  const unsigned hb = (unsigned)std::min<int64_t>(w.n_blocks, 2048);
+  radix_histogram<<<dim3(hb), 256, 0, s>>>(b.keys[src0], count, max_items, passes, db, w.hist);
+  radix_scan_hist<<<1, 256, 0, s>>>(w.hist, passes);
+  const dim3 grid((unsigned)w.n_blocks);
+  for (int p = 0; p < passes; ++p) {
+    const int src = (start + p) & 1, dst = src ^ 1;
+    uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
+#define GS_LAUNCH_PASS(D)                                                                        \
+  radix_pass<D><<<grid, kSortBlock, 0, s>>>(b.keys[src], b.vals[src], b.keys[dst], b.vals[dst],  \
+                                            count, max_items, p * db, w.hist + p * 256, lb,      \
+                                            w.ticket + p, status)
+    switch (db) {
+      case 4: GS_LAUNCH_PASS(4); break;
+      case 5: GS_LAUNCH_PASS(5); break;
+      case 6: GS_LAUNCH_PASS(6); break;
+      case 7: GS_LAUNCH_PASS(7); break;
+      default: GS_LAUNCH_PASS(8); break;
+    }
+#undef GS_LAUNCH_PASS
+  }
+  return GS_OK;
+}
+
 // IdentifyTileRanges: [start, end) of every global tile by binary search of the
-// sorted keys (equivalent to comparing neighbouring tile ids; no zero-fill needed).
+// sorted tile ids (equivalent to comparing neighbouring ids; no zero-fill needed).
 __global__ void __launch_bounds__(256)
-sort_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count, int64_t capacity,
-            int64_t n_tiles, uint32_t* __restrict__ ranges) {
+sort_ranges(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ count,
+            int64_t capacity, int64_t n_tiles, uint32_t* __restrict__ ranges) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= n_tiles) return;
   const int64_t M = min((int64_t)count[0], capacity);
-  auto lower = [&](uint64_t key) {
+  auto lower = [&](uint32_t key) {
     int64_t lo = 0, hi = M;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
-      if (keys[mid] < key) lo = mid + 1; else hi = mid;
+      if (tiles[mid] < key) lo = mid + 1; else hi = mid;
     }
     return lo;
   };
-  ranges[2 * t] = (uint32_t)lower((uint64_t)t << 32);
-  ranges[2 * t + 1] = (uint32_t)lower((uint64_t)(t + 1) << 32);
+  ranges[2 * t] = (uint32_t)lower((uint32_t)t);
+  ranges[2 * t + 1] = (uint32_t)lower((uint32_t)(t + 1));
 }
 
 // Issue order for the render launches: tiles bucketed by floor(log2(list length)),
@@ -302,17 +349,44 @@ sort_tile_order(const uint32_t* __restrict__ ranges, int64_t n_tiles, uint32_t* 
   }
 }
 
+int tile_key_bits(int64_t n_tiles_total) {
+  int tb = 0;
+  while (tb < 40 && ((int64_t)1 << tb) < n_tiles_total) ++tb;
+  return tb;
+}
+
+InstanceBufs instance_bufs(const gs_instances* inst, int tile_passes) {
+  // keys / keys_alt hold capacity 64-bit words each; each is used as two u32 arrays
+  InstanceBufs b;
+  uint32_t* k0 = reinterpret_cast<uint32_t*>(inst->keys);
+  uint32_t* k1 = reinterpret_cast<uint32_t*>(inst->keys_alt);
+  const int64_t cap = inst->capacity;
+  b.depth = {{k0, k1}, {k0 + cap, k1 + cap}};
+  // the expansion writes (k1, vals or vals_alt) so that the tile passes end in vals
+  const bool odd = tile_passes & 1;
+  b.tiles = {{k1, k0}, {odd ? inst->vals_alt : inst->vals, odd ? inst->vals : inst->vals_alt}};
+  b.sorted_tiles = odd ? k0 : k1;
+  return b;
+}
+
 }  // namespace gs
 
 using namespace gs;
 
+extern "C" int32_t gs_sort_key_bits(int64_t n_tiles_total) { return tile_key_bits(n_tiles_total); }
+
 extern "C" size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total,
                                           const gs_config* cfg) {
   if (capacity < 0 || !cfg || check_config(cfg) != GS_OK) return 0;
-  const int passes = sort_passes(n_tiles_total, cfg->sort_digit_bits);
-  int64_t nb = (capacity + kSortTile - 1) / kSortTile;
-  if (nb < 1) nb = 1;
-  return (size_t)(kMaxPasses * 256 + 64 + (int64_t)passes * nb * 256) * sizeof(uint32_t);
+  const int passes = radix_passes(tile_key_bits(n_tiles_total), cfg->sort_digit_bits);
+  return radix_workspace_bytes(capacity, passes);
+}
+
+extern "C" const uint32_t* gs_sorted_tile_ids(const gs_instances* inst, int64_t n_tiles_total,
+                                              const gs_config* cfg) {
+  if (!inst || !cfg || check_config(cfg) != GS_OK || !inst->keys || !inst->keys_alt) return nullptr;
+  return instance_bufs(inst, radix_passes(tile_key_bits(n_tiles_total), cfg->sort_digit_bits))
+      .sorted_tiles;
 }
 
 extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
@@ -327,43 +401,17 @@ extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs
   if (inst->capacity > GS_MAX_INSTANCES) return GS_ERR_UNSUPPORTED;
   if (n_tiles_total >= ((int64_t)1 << 31)) return GS_ERR_UNSUPPORTED;
   if (workspace_bytes < gs_sort_workspace_bytes(inst->capacity, n_tiles_total, cfg)) return GS_ERR_ARG;
-  const int db = cfg->sort_digit_bits;
-  const int passes = sort_passes(n_tiles_total, db);
+  const int bits = tile_key_bits(n_tiles_total);
+  const int passes = radix_passes(bits, cfg->sort_digit_bits);
   if (passes > kMaxPasses) return GS_ERR_UNSUPPORTED;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SortWs w = carve(workspace, inst->capacity);
+  const InstanceBufs b = instance_bufs(inst, passes);
   const int64_t cap = inst->capacity;
-  sort_init<<<dim3((unsigned)std::min<int64_t>(std::max<int64_t>(w.n_blocks, 1), 1024)), 256, 0, s>>>(
-      w, passes, inst->count, cap);
-  // gs_bin leaves the unsorted instances where an even number of ping-pong passes
-  // ends in keys/vals
-  const bool odd = passes & 1;
-  uint64_t* kb[2] = {odd ? inst->keys_alt : inst->keys, odd ? inst->keys : inst->keys_alt};
-  uint32_t* vb[2] = {odd ? inst->vals_alt : inst->vals, odd ? inst->vals : inst->vals_alt};
-  if (cap > 0) {
-    const unsigned hb = (unsigned)std::min<int64_t>((cap + 4095) / 4096, 2048);
-    sort_histogram<<<dim3(hb), 256, 0, s>>>(kb[0], inst->count, cap, passes, db, w.hist);
-    sort_scan_hist<<<1, 256, 0, s>>>(w.hist, passes);
-    const dim3 grid((unsigned)w.n_blocks);
-    for (int p = 0; p < passes; ++p) {
-      const int src = p & 1, dst = src ^ 1;
-      uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
-#define GS_LAUNCH_PASS(D)                                                                       \
-  sort_pass<D><<<grid, kSortBlock, 0, s>>>(kb[src], vb[src], kb[dst], vb[dst], inst->count, cap, \
-                                           p * db, w.hist + p * 256, lb, w.ticket + p,          \
-                                           inst->status)
-      switch (db) {
-        case 4: GS_LAUNCH_PASS(4); break;
-        case 5: GS_LAUNCH_PASS(5); break;
-        case 6: GS_LAUNCH_PASS(6); break;
-        case 7: GS_LAUNCH_PASS(7); break;
-        default: GS_LAUNCH_PASS(8); break;
-      }
-#undef GS_LAUNCH_PASS
-    }
-  }
+  rc = radix_sort(b.tiles, 0, inst->count, cap, bits, cfg->sort_digit_bits, workspace,
+                  workspace_bytes, inst->status, s);
+  if (rc != GS_OK) return rc;
   sort_ranges<<<dim3((unsigned)((n_tiles_total + 255) / 256)), 256, 0, s>>>(
-      inst->keys, inst->count, cap, n_tiles_total, tile_ranges);
+      b.sorted_tiles, inst->count, cap, n_tiles_total, tile_ranges);
   if (tile_order) sort_tile_order<<<1, 1024, 0, s>>>(tile_ranges, n_tiles_total, tile_order);
   return launch_status();
 }

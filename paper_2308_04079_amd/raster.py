@@ -83,6 +83,19 @@ class RenderState:
                                 _lib.ptr(self.vals_alt), self.capacity, _lib.ptr(self.count),
                                 _lib.ptr(self.status))
 
+    def tile_ids(self, cfg) -> torch.Tensor:
+        """Sorted global tile id of every instance (int32 view of the scratch buffer)."""
+        inst = self.instances()
+        addr = _lib.lib().gs_sorted_tile_ids(ctypes.byref(inst), self.n_tiles, ctypes.byref(cfg))
+        if not addr:
+            raise _lib.GsError("gs_sorted_tile_ids", _lib.ERR_ARG)
+        for buf in (self.keys, self.keys_alt):
+            words = buf.view(torch.int32)
+            off = (addr - buf.data_ptr()) // 4
+            if 0 <= off < words.numel():
+                return words[off:off + self.capacity]
+        raise RuntimeError("sorted tile ids outside the instance buffers")
+
     def view_image(self, v: int) -> torch.Tensor:
         c = self.cams[v]
         p = self.pix_offset[v]
@@ -158,7 +171,7 @@ class Rasterizer:
         npix = pix[-1] if for_backward else 0
         T_final = torch.empty(npix, dtype=torch.float32, device=dev)
         last_idx = torch.empty(npix, dtype=torch.int32, device=dev)
-        bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n)), dtype=torch.uint8,
+        bin_ws = torch.empty(max(1, lib.gs_bin_workspace_bytes(V * n, cfg)), dtype=torch.uint8,
                              device=dev)
         while True:
             cap = min(int(cap), _lib.MAX_INSTANCES)

@@ -64,9 +64,9 @@ def test_tile_layout_and_key_bits(L):
     off = (ctypes.c_int64 * 3)()
     n = L.lib().gs_tile_layout(cc, 2, 16, off)
     assert list(off) == [0, 120 * 68, 120 * 68 + 3 * 2] and n == off[2]
-    assert L.lib().gs_sort_key_bits(8160) == 31 + 13
-    assert L.lib().gs_sort_key_bits(64) == 31 + 6
-    assert L.lib().gs_sort_key_bits(1) == 31
+    assert L.lib().gs_sort_key_bits(8160) == 13
+    assert L.lib().gs_sort_key_bits(64) == 6
+    assert L.lib().gs_sort_key_bits(1) == 0
     assert L.lib().gs_tile_layout(cc, 2, 12, None) == L.ERR_ARG
     assert L.lib().gs_tile_layout(cc, 0, 16, None) == L.ERR_ARG
 
@@ -93,7 +93,11 @@ def test_host_argument_checks_return_before_any_launch(L):
     huge = L.make_cameras([scenes.pinhole_camera(40000, 8)])
     assert lib.gs_render_fwd(ctypes.byref(proj), ctypes.byref(inst), 1, None, huge, 1, ctypes.byref(cfg), 1, 1, 1, 1, None) == L.ERR_UNSUPPORTED
     assert lib.gs_sort(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, None, 0, None) == L.ERR_ARG
-    assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) > (1 << 20) // 4096 * 6 * 1024
+    # two 8-bit passes over the 13 tile-id bits of one 1080p view
+    assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) > (1 << 20) // 4096 * 2 * 1024
+    assert lib.gs_sort_key_bits(8160) == 13 and lib.gs_sort_key_bits(1) == 0
+    assert lib.gs_bin_workspace_bytes(1000, ctypes.byref(cfg)) > 0
+    assert lib.gs_bin_workspace_bytes(1000, ctypes.byref(bad)) == 0
     assert lib.gs_status_string(L.ERR_CAPACITY) == b"instance count exceeds capacity"
 
 

@@ -35,7 +35,8 @@ def test_full_sort_bit_exact(full):
     M = int(to_np(state.count)[0])
     ek, ev = expected_sorted_instances(state)
     assert M == ek.size
-    assert np.array_equal(to_np(state.keys)[:M].view(np.uint64), ek)
+    assert np.array_equal(to_np(state.tile_ids(rast.cfg))[:M].astype(np.int64),
+                          (ek >> np.uint64(32)).astype(np.int64))
     assert np.array_equal(to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF, ev)
     check_ranges(state, ek)
     # depth keys of every visible Gaussian are the oracle's, bit for bit

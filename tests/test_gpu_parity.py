@@ -53,7 +53,8 @@ def test_project_matches_oracle(name):
 
 
 def expected_sorted_instances(state, tile=16):
-    """Instances built in NumPy from the GPU's own projection, sorted by (key, value)."""
+    """Instances built in NumPy from the GPU's own projection, sorted by the paper's
+    single key (tile << 32 | depth), ties by value."""
     keys, vals = [], []
     for v, cam in enumerate(state.cams):
         g = decode_records(state, v)
@@ -77,13 +78,13 @@ def expected_sorted_instances(state, tile=16):
 @pytest.mark.parametrize("name", list(CASES))
 def test_sort_and_ranges_bit_exact(name):
     sc, cams = CASES[name]
-    _, _, state = gpu_render(sc, cams)
+    rast, _, state = gpu_render(sc, cams)
     M = int(to_np(state.count)[0])
     ek, ev = expected_sorted_instances(state)
     assert M == ek.size
-    gk = to_np(state.keys)[:M].view(np.uint64)
+    gt = to_np(state.tile_ids(rast.cfg))[:M].astype(np.int64)
     gv = to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF
-    assert np.array_equal(gk, ek)
+    assert np.array_equal(gt, (ek >> np.uint64(32)).astype(np.int64))
     assert np.array_equal(gv, ev)
     check_ranges(state, ek)
 
