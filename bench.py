@@ -26,7 +26,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # FP32 vector issue rate without packed-FP32 instructions: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 vector peak in lane operations per second (an FMA counted once): the published
+# 157.3 TFLOP/s (an FMA counted as two flops) = 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.
+# The kernels reach VALU issue rates above the 16-lanes-per-SIMD figure, so the
+# 32-lane figure is the ceiling that applies.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
 
 WORKLOAD_TEXT = {
