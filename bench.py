@@ -47,8 +47,8 @@ WORKLOAD_TEXT = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--views", type=int, default=4)
     ap.add_argument("--n", type=int, default=None, help="Gaussians (default: the workload's)")
     ap.add_argument("--workload", choices=("train4", "full1080", "multiview"), default="train4")
