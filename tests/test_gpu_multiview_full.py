@@ -86,3 +86,25 @@ def test_sort_digit_width_does_not_change_the_order(bits):
     assert M == int(to_np(b.count)[0])
     np.testing.assert_array_equal(to_np(a.vals)[:M], to_np(b.vals)[:M])
     np.testing.assert_array_equal(to_np(a.ranges), to_np(b.ranges))
+
+
+@pytest.mark.parametrize("n", [6000, 13000])
+def test_long_tile_lists_and_depth_ties(n):
+    # every Gaussian covers all 16 tiles of a 64x64 view, so each list holds n entries;
+    # 200 of them share one depth (the index decides)
+    from tests.helpers import make_scene
+    rng = np.random.default_rng(n)
+    mu = np.stack([rng.uniform(-0.05, 0.05, n), rng.uniform(-0.05, 0.05, n),
+                   rng.uniform(3.0, 3.5, n)], 1)
+    mu[n // 2:n // 2 + 200, 2] = mu[n // 2, 2]
+    sc = make_scene(mu, np.full((n, 3), np.log(1.5)), np.tile([1.0, 0, 0, 0], (n, 1)),
+                    rng.normal(-4.0, 0.5, n), rng.uniform(-1, 1, (n, 1, 3)))
+    cams = [scenes.pinhole_camera(64, 64)]
+    rast, _, state = gpu_render(sc, cams)
+    M = int(to_np(state.count)[0])
+    ek, ev = expected_sorted_instances(state)
+    assert M == ek.size == 16 * n
+    assert np.array_equal(to_np(state.tile_ids(rast.cfg))[:M].astype(np.int64),
+                          (ek >> np.uint64(32)).astype(np.int64))
+    assert np.array_equal(to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF, ev)
+    check_ranges(state, ek)
