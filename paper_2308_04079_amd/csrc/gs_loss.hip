@@ -46,6 +46,14 @@ __device__ __forceinline__ void stage_planes(const float* const (&src)[NM], int 
   }
 }
 
+// Both passes are register blocked: in the horizontal pass a thread produces four
+// neighbouring columns of a row from 14 staged values, in the vertical pass four
+// neighbouring rows of a column, so each staged value is read from LDS about 3.5
+// times instead of 11. Lanes walk rows (horizontal) or columns (vertical), which keeps
+// the LDS accesses free of bank conflicts (odd row strides).
+constexpr int kLB = 4;                          // outputs per thread along the pass
+constexpr int kLW = kLB + 2 * kLR;              // staged values per thread (14)
+
 __global__ void __launch_bounds__(kLThreads)
 ssim_moments_kernel(const float* __restrict__ image, const float* __restrict__ target,
                     TileViews tv, LossArgs la, float* __restrict__ partials,
@@ -64,25 +72,33 @@ ssim_moments_kernel(const float* __restrict__ image, const float* __restrict__ t
   stage_planes<2>(src, W, H, x0, y0, s_in);
   __syncthreads();
 
-  // horizontal pass: 42 rows x 32 columns of the five moments
-  for (int k = threadIdx.x; k < kLI * kLT; k += kLThreads) {
-    const int r = k / kLT, q = k - r * kLT;
-    float mx = 0.0f, my = 0.0f, xx = 0.0f, yy = 0.0f, xy = 0.0f;
+  // horizontal pass: 42 rows x 32 columns of the five moments, four columns per item
+  for (int k = threadIdx.x; k < kLI * (kLT / kLB); k += kLThreads) {
+    const int r = k % kLI, q0 = (k / kLI) * kLB;
+    float xv[kLW], yv[kLW];
 #pragma unroll
-    for (int b = 0; b <= 2 * kLR; ++b) {
-      const float xv = s_in[0][r][q + b], yv = s_in[1][r][q + b], w = la.g[b];
-      const float wx = w * xv, wy = w * yv;
-      mx += wx;
-      my += wy;
-      xx = fmaf(wx, xv, xx);
-      yy = fmaf(wy, yv, yy);
-      xy = fmaf(wx, yv, xy);
+    for (int j = 0; j < kLW; ++j) {
+      xv[j] = s_in[0][r][q0 + j];
+      yv[j] = s_in[1][r][q0 + j];
     }
-    s_h[0][r][q] = mx;
-    s_h[1][r][q] = my;
-    s_h[2][r][q] = xx;
-    s_h[3][r][q] = yy;
-    s_h[4][r][q] = xy;
+#pragma unroll
+    for (int o = 0; o < kLB; ++o) {
+      float mx = 0.0f, my = 0.0f, xx = 0.0f, yy = 0.0f, xy = 0.0f;
+#pragma unroll
+      for (int b = 0; b <= 2 * kLR; ++b) {
+        const float w = la.g[b], wx = w * xv[o + b], wy = w * yv[o + b];
+        mx += wx;
+        my += wy;
+        xx = fmaf(wx, xv[o + b], xx);
+        yy = fmaf(wy, yv[o + b], yy);
+        xy = fmaf(wx, yv[o + b], xy);
+      }
+      s_h[0][r][q0 + o] = mx;
+      s_h[1][r][q0 + o] = my;
+      s_h[2][r][q0 + o] = xx;
+      s_h[3][r][q0 + o] = yy;
+      s_h[4][r][q0 + o] = xy;
+    }
   }
   __syncthreads();
 
@@ -91,35 +107,47 @@ ssim_moments_kernel(const float* __restrict__ image, const float* __restrict__ t
   const float* Y = src[1];
   float part = 0.0f;
   const int64_t P = 3 * tv.pix_offset[tv.n_views];   // values per partial map
-  for (int k = threadIdx.x; k < kLT * kLT; k += kLThreads) {
-    const int r = k / kLT, q = k - r * kLT;
-    const int gy = y0 + r, gx = x0 + q;
-    if (gy >= H || gx >= W) continue;
-    float m[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  // vertical pass: 32 columns x 8 groups of four rows, one item per thread
+  {
+    const int q = threadIdx.x % kLT, r0 = (threadIdx.x / kLT) * kLB;
+    float m[5][kLB];
 #pragma unroll
-    for (int a = 0; a <= 2 * kLR; ++a) {
-      const float w = la.g[a];
+    for (int j = 0; j < 5; ++j) {
+      float col[kLW];
 #pragma unroll
-      for (int j = 0; j < 5; ++j) m[j] = fmaf(w, s_h[j][r + a][q], m[j]);
+      for (int a = 0; a < kLW; ++a) col[a] = s_h[j][r0 + a][q];
+#pragma unroll
+      for (int o = 0; o < kLB; ++o) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int a = 0; a <= 2 * kLR; ++a) acc = fmaf(la.g[a], col[o + a], acc);
+        m[j][o] = acc;
+      }
     }
-    const float mx = m[0], my = m[1];
-    const float a1 = 2.0f * mx * my + kC1;
-    const float a2 = 2.0f * (m[4] - mx * my) + kC2;
-    const float b1 = mx * mx + my * my + kC1;
-    const float b2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
-    const float den = b1 * b2;
-    const float iden = 1.0f / den;
-    const float S = a1 * a2 * iden;
-    // dS/dmu_x, dS/dE[x^2], dS/dE[xy]
-    const float d_mx = 2.0f * my * (a2 - a1) * iden - 2.0f * mx * S * (b2 - b1) * iden;
-    const float d_xx = -S / b2;
-    const float d_xy = 2.0f * a1 * iden;
-    const int64_t o = plane + (int64_t)gy * W + gx;
-    partials[o] = d_mx;
-    partials[P + o] = d_xx;
-    partials[2 * P + o] = d_xy;
-    const float d = X[(int64_t)gy * W + gx] - Y[(int64_t)gy * W + gx];
-    part += ((1.0f - la.lambda) * fabsf(d) + la.lambda * (1.0f - S)) * inv;
+    const int gx = x0 + q;
+#pragma unroll
+    for (int o = 0; o < kLB; ++o) {
+      const int gy = y0 + r0 + o;
+      if (gy >= H || gx >= W) continue;
+      const float mx = m[0][o], my = m[1][o];
+      const float a1 = 2.0f * mx * my + kC1;
+      const float a2 = 2.0f * (m[4][o] - mx * my) + kC2;
+      const float b1 = mx * mx + my * my + kC1;
+      const float b2 = (m[2][o] - mx * mx) + (m[3][o] - my * my) + kC2;
+      const float den = b1 * b2;
+      const float iden = 1.0f / den;
+      const float S = a1 * a2 * iden;
+      // dS/dmu_x, dS/dE[x^2], dS/dE[xy]
+      const float d_mx = 2.0f * my * (a2 - a1) * iden - 2.0f * mx * S * (b2 - b1) * iden;
+      const float d_xx = -S / b2;
+      const float d_xy = 2.0f * a1 * iden;
+      const int64_t o_ = plane + (int64_t)gy * W + gx;
+      partials[o_] = d_mx;
+      partials[P + o_] = d_xx;
+      partials[2 * P + o_] = d_xy;
+      const float d = X[(int64_t)gy * W + gx] - Y[(int64_t)gy * W + gx];
+      part += ((1.0f - la.lambda) * fabsf(d) + la.lambda * (1.0f - S)) * inv;
+    }
   }
   if (loss) {
     part = wave_sum_to_lane63(part);
@@ -146,37 +174,50 @@ ssim_grad_kernel(const float* __restrict__ image, const float* __restrict__ targ
   const float* const src[3] = {partials + plane, partials + P + plane, partials + 2 * P + plane};
   stage_planes<3>(src, W, H, x0, y0, s_in);
   __syncthreads();
-  for (int k = threadIdx.x; k < kLI * kLT; k += kLThreads) {
-    const int r = k / kLT, q = k - r * kLT;
-    float f[3] = {0.0f, 0.0f, 0.0f};
+  for (int k = threadIdx.x; k < kLI * (kLT / kLB); k += kLThreads) {
+    const int r = k % kLI, q0 = (k / kLI) * kLB;
 #pragma unroll
-    for (int b = 0; b <= 2 * kLR; ++b) {
-      const float w = la.g[b];
+    for (int j = 0; j < 3; ++j) {
+      float row[kLW];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) f[j] = fmaf(w, s_in[j][r][q + b], f[j]);
+      for (int b = 0; b < kLW; ++b) row[b] = s_in[j][r][q0 + b];
+#pragma unroll
+      for (int o = 0; o < kLB; ++o) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int b = 0; b <= 2 * kLR; ++b) acc = fmaf(la.g[b], row[o + b], acc);
+        s_h[j][r][q0 + o] = acc;
+      }
     }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) s_h[j][r][q] = f[j];
   }
   __syncthreads();
   const float inv = 1.0f / (3.0f * (float)HW);
   const float l1w = (1.0f - la.lambda) * inv, sw = -la.lambda * inv;
-  for (int k = threadIdx.x; k < kLT * kLT; k += kLThreads) {
-    const int r = k / kLT, q = k - r * kLT;
-    const int gy = y0 + r, gx = x0 + q;
-    if (gy >= H || gx >= W) continue;
-    float f[3] = {0.0f, 0.0f, 0.0f};
+  const int q = threadIdx.x % kLT, r0 = (threadIdx.x / kLT) * kLB;
+  float f[3][kLB];
 #pragma unroll
-    for (int a = 0; a <= 2 * kLR; ++a) {
-      const float w = la.g[a];
+  for (int j = 0; j < 3; ++j) {
+    float col[kLW];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) f[j] = fmaf(w, s_h[j][r + a][q], f[j]);
+    for (int a = 0; a < kLW; ++a) col[a] = s_h[j][r0 + a][q];
+#pragma unroll
+    for (int o = 0; o < kLB; ++o) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int a = 0; a <= 2 * kLR; ++a) acc = fmaf(la.g[a], col[o + a], acc);
+      f[j][o] = acc;
     }
-    const int64_t o = plane + (int64_t)gy * W + gx;
-    const float x = image[o], y = target[o];
+  }
+  const int gx = x0 + q;
+#pragma unroll
+  for (int o = 0; o < kLB; ++o) {
+    const int gy = y0 + r0 + o;
+    if (gy >= H || gx >= W) continue;
+    const int64_t o_ = plane + (int64_t)gy * W + gx;
+    const float x = image[o_], y = target[o_];
     const float d = x - y;
     const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-    dL[o] = l1w * sg + sw * (f[0] + 2.0f * x * f[1] + y * f[2]);
+    dL[o_] = l1w * sg + sw * (f[0][o] + 2.0f * x * f[1][o] + y * f[2][o]);
   }
 }
 
