@@ -231,7 +231,10 @@ int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
  * given dL/dimage in the image layout, accumulates per view and Gaussian the
  * screen-space gradient record grad2d[v*N + g][9] =
  *   d(u, v), d(w00, w10, w11), d(opacity), d(r, g, b).
- * The gradients are ADDED to grad2d: the caller zeroes it first. */
+ * The gradients are ADDED to grad2d: the caller zeroes it first. T_final and
+ * last_idx are the forward pass's outputs for the same inputs; a last_idx beyond
+ * its tile's instance list is treated as the list's end (the walk never leaves
+ * the list), other values give meaningless gradients but no out-of-range access. */
 int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
                   const uint32_t* tile_ranges, const uint32_t* tile_order,
                   const gs_camera* cams, int32_t n_views,

@@ -280,7 +280,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const uint32_t start = ranges[2 * w.tile];
+  const uint32_t start = ranges[2 * w.tile], end = ranges[2 * w.tile + 1];
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
   int32_t last = -1;
@@ -298,8 +298,10 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   // only g . B is ever needed, where B is the colour accumulated behind the current
   // Gaussian (initially T_final bg): dC/dalpha_i . g = T_i (g . c_i) - (g . B_i) / (1 - alpha_i)
   float S = T * (g0 * rules.bg[0] + g1 * rules.bg[1] + g2 * rules.bg[2]);
-  const int wave_last = wave_max_int(last);
-  if (wave_last < (int)start) return;  // no pixel of this wave blended anything
+  // the walk starts at the wave's last contributor, bounded by the tile's list so that
+  // a last_idx not written by the forward pass cannot send the gathers out of range
+  const int64_t wave_last = std::min<int64_t>(wave_max_int(last), (int64_t)end - 1);
+  if (wave_last < (int64_t)start) return;  // no pixel of this wave blended anything
   const bool atomic_lane = lane < 16 && ((kReduceLanes >> lane) & 1u);
   const int atomic_slot = reduce_index((uint32_t)lane);
   // limited-gradient ablation: count the pixel's blended Gaussians first, so the
