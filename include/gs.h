@@ -217,8 +217,11 @@ const uint32_t* gs_sorted_tile_ids(const gs_instances* inst, int64_t n_tiles_tot
  *   T_final  [H][W] at T_final + P_v        final transmittance
  *   last_idx [H][W] at last_idx + P_v       instance position of the last
  *                                           blended Gaussian, -1 if none
- * n is N (per view); instance values >= V*N are ignored. tile_order (device,
- * nullable) is the order in which tiles are issued (from gs_sort); it changes no
+ * n is N (per view); instance values >= V*N are ignored, and tile ranges are
+ * clipped to [0, inst->capacity] (GS_ERR_ARG for a capacity outside
+ * 0..GS_MAX_INSTANCES), so ranges not written by gs_sort give wrong images but
+ * no out-of-range access. tile_order (device, nullable) is the order in which
+ * tiles are issued (from gs_sort, a permutation of the tile ids); it changes no
  * output. */
 int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
                   const uint32_t* tile_ranges, const uint32_t* tile_order,

@@ -35,6 +35,7 @@ struct TileViews {
   int32_t tile_offset[GS_MAX_VIEWS + 1];
   int64_t pix_offset[GS_MAX_VIEWS + 1];
   uint32_t n_records;  // V * N: instance values at or above it are ignored
+  uint32_t n_inst;     // instance capacity: tile ranges are clipped to it
 };
 
 struct Rules {

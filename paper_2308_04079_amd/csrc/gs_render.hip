@@ -55,6 +55,7 @@ template <int TS>
 __device__ __forceinline__ bool wave_tile(const TileViews& tv, const uint32_t* tile_order,
                                           WaveTile& w) {
   w.tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;
+  if ((uint32_t)w.tile >= (uint32_t)tv.tile_offset[tv.n_views]) return false;  // not a tile id
   w.n_records = tv.n_records;
   w.v = view_of_tile(tv, w.tile);
   const int lt = w.tile - tv.tile_offset[w.v];
@@ -72,6 +73,14 @@ __device__ __forceinline__ bool wave_tile(const TileViews& tv, const uint32_t* t
   w.py = w.y0 + (lane >> 3);
   w.inside = (w.px < w.W) && (w.py < w.H);
   return true;
+}
+
+// The tile's instance list [start, end), clipped to the instance buffers, so that
+// ranges not written by gs_sort cannot send the gathers out of range.
+__device__ __forceinline__ void tile_range(const uint32_t* __restrict__ ranges, int tile,
+                                           uint32_t n_inst, uint32_t& start, uint32_t& end) {
+  end = min(ranges[2 * tile + 1], n_inst);
+  start = min(ranges[2 * tile], end);
 }
 
 // One list entry as gathered by a lane: kept if its 3-sigma ellipse can reach the
@@ -176,7 +185,8 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave;
-  const uint32_t start = ranges[2 * w.tile], end = ranges[2 * w.tile + 1];
+  uint32_t start, end;
+  tile_range(ranges, w.tile, tv.n_inst, start, end);
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int32_t last = -1;
@@ -280,7 +290,8 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const uint32_t start = ranges[2 * w.tile], end = ranges[2 * w.tile + 1];
+  uint32_t start, end;
+  tile_range(ranges, w.tile, tv.n_inst, start, end);
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
   int32_t last = -1;
@@ -411,6 +422,8 @@ static int render_common(const gs_projected* proj, const gs_instances* inst,
   if (n * (int64_t)n_views >= ((int64_t)1 << 32)) return GS_ERR_UNSUPPORTED;
   tv->n_records = (uint32_t)(n * n_views);
   if (!proj->record || !inst->vals) return GS_ERR_ARG;
+  if (inst->capacity < 0 || inst->capacity > GS_MAX_INSTANCES) return GS_ERR_ARG;
+  tv->n_inst = (uint32_t)inst->capacity;
   return GS_OK;
 }
 

@@ -257,3 +257,75 @@ def test_l1_loss_gradient():
         k = 3 * cam.width * cam.height
         np.testing.assert_allclose(dL[sl], np.sign(img[sl] - tgt[sl]) / k, rtol=1e-6, atol=0)
         np.testing.assert_allclose(to_np(loss)[v], np.abs(img[sl] - tgt[sl]).mean(), rtol=1e-5)
+
+
+def test_backward_walk_is_bounded_by_the_tile_list():
+    """A last_idx past its tile's instance list acts as the list's last entry: the
+    backward walk starts there, and the gradients equal those of that clamped input."""
+    import dataclasses
+
+    import torch
+    sc, cams = CASES["ragged"]
+    rast, params, state = gpu_render(sc, cams)
+    cam = cams[0]
+    W, H, T = cam.width, cam.height, 16
+    ranges = to_np(state.ranges).astype(np.int64).reshape(-1, 2)
+    last = to_np(state.last_idx).astype(np.int64)
+    ys, xs = np.divmod(np.arange(W * H), W)
+    tile = state.tile_offset[0] + (ys // T) * ((W + T - 1) // T) + xs // T
+    hit = last >= 0
+    assert hit.sum() > 100
+    huge = np.where(hit, 2 ** 31 - 1, last)
+    clamped = np.where(hit, ranges[tile, 1] - 1, last)
+    w = np.random.default_rng(7).standard_normal(3 * W * H).astype(np.float32)
+    dimg = torch.from_numpy(w).cuda()
+    out = []
+    for li in (huge, clamped):
+        st = dataclasses.replace(state, last_idx=torch.from_numpy(li.astype(np.int32)).cuda())
+        grads, _ = rast.backward(params, st, dimg)
+        torch.cuda.synchronize()
+        out.append({k: to_np(grads[k]).astype(np.float64) for k in GROUPS})
+    for k in GROUPS:
+        assert np.abs(out[0][k]).max() > 0, k
+        assert rel_l2(out[0][k], out[1][k]) <= 1e-5, k
+
+
+def test_blend_kernels_clip_ranges_and_tile_order_they_did_not_get_from_the_sort():
+    """Tile ranges and a tile order that gs_sort did not write are clipped by the
+    kernels: every list becomes [0, capacity) (values past the instance count are
+    whatever the buffer holds; entries >= V N are skipped), tile-order entries that are
+    no tile id issue nothing. The calls complete and what they write is finite."""
+    import ctypes
+    import dataclasses
+
+    import torch
+    from paper_2308_04079_amd import _lib
+    sc, cams = CASES["ragged"]
+    rast, params, state = gpu_render(sc, cams)
+    ranges = state.ranges.clone().view(-1, 2)
+    ranges[:, 0] = 0
+    ranges[:, 1] = -1                                   # 0xFFFFFFFF
+    order = state.order.clone()
+    order[::3] = -1                                     # not a tile id: skipped
+    bad = dataclasses.replace(state, ranges=ranges.reshape(-1), order=order)
+    image = torch.full_like(state.image, 7.0)
+    lib = _lib.lib()
+    proj = _lib.GsProjected(_lib.ptr(bad.depth_key), _lib.ptr(bad.tiles_touched),
+                            _lib.ptr(bad.record))
+    inst = bad.instances()
+    stream = torch.cuda.current_stream().cuda_stream
+    _lib.check("gs_render_fwd", lib.gs_render_fwd(
+        ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(bad.ranges), _lib.ptr(bad.order),
+        bad.cams_c, bad.n_views, ctypes.byref(rast.cfg), _lib.ptr(image), _lib.ptr(bad.T_final),
+        _lib.ptr(bad.last_idx), bad.n, stream))
+    torch.cuda.synchronize()
+    img = to_np(image)
+    assert np.isfinite(img).all()
+    assert (img == 7.0).any() and (img != 7.0).any()   # skipped tiles kept the fill
+    last = to_np(bad.last_idx)
+    assert last.max() < bad.capacity
+    w = torch.ones(state.image.numel(), device="cuda")
+    grads, _ = rast.backward(params, bad, w)
+    torch.cuda.synchronize()
+    for k in GROUPS:
+        assert np.isfinite(to_np(grads[k])).all(), k
