@@ -359,9 +359,10 @@ def processed_pairs(st, cfg, T=16):
 
     A wave owns an 8x8 pixel block of a tile; it walks the tile's list from the
     block's last contributor back to the start and evaluates (on all 64 lanes)
-    every entry whose 3-sigma pixel box meets its block and whose second whitened
-    coordinate is not beyond 3 sigma at all four block corners (the kernel's two
-    staging tests, replayed here in FP64).
+    every entry whose 3-sigma pixel box meets its block and whose least Mahalanobis
+    distance m over the block's pixel-centre rectangle is within
+    min(9, 2 ln(o / alpha_min)) (the kernel's two staging tests, replayed here in
+    FP64 without the kernel's rounding slack).
     """
     import torch
     dev = st.ranges.device
@@ -373,7 +374,9 @@ def processed_pairs(st, cfg, T=16):
     hi = rec[vals, 1].view(torch.int32).long()
     ilo, jlo, ihi, jhi = lo & 0xFFFF, (lo >> 16) & 0xFFFF, hi & 0xFFFF, (hi >> 16) & 0xFFFF
     mx, my = rec[vals, 2].double(), rec[vals, 3].double()
-    w10, w11 = rec[vals, 5].double(), rec[vals, 6].double()
+    w00, w10, w11 = rec[vals, 4].double(), rec[vals, 5].double(), rec[vals, 6].double()
+    opac = rec[vals, 7].double()
+    thr_all = torch.clamp(2.0 * (torch.log(opac) - math.log(cfg.alpha_min)), max=cfg.sigma_extent ** 2)
     pos = torch.arange(M, device=dev)
     toff = torch.tensor(st.tile_offset, device=dev)
     view = torch.searchsorted(toff, tile, right=True) - 1
@@ -402,10 +405,21 @@ def processed_pairs(st, cfg, T=16):
                 dxb = (x1 - ilo[sel]) + 0.5 - mx[sel]
                 dya = (y0 - jlo[sel]) + 0.5 - my[sel]
                 dyb = (y1 - jlo[sel]) + 0.5 - my[sel]
-                e = torch.stack([w10[sel] * dxa + w11[sel] * dya, w10[sel] * dxb + w11[sel] * dya,
-                                 w10[sel] * dxa + w11[sel] * dyb, w10[sel] * dxb + w11[sel] * dyb])
-                lim = 3.0 * 1.00001
-                ov &= ~((e.min(0).values > lim) | (e.max(0).values < -lim))
+                a00, a10, a11 = w00[sel], w10[sel], w11[sel]
+
+                def edge_x(X):   # least m on the edge dx = X: vertex of the parabola, clamped
+                    dy = torch.minimum(torch.maximum(-a10 * X / a11, dya), dyb)
+                    return (a00 * X) ** 2 + (a10 * X + a11 * dy) ** 2
+
+                def edge_y(Y):
+                    dx = torch.minimum(torch.maximum(-a10 * a11 * Y / (a00 ** 2 + a10 ** 2), dxa), dxb)
+                    return (a00 * dx) ** 2 + (a10 * dx + a11 * Y) ** 2
+
+                mmin = torch.minimum(torch.minimum(edge_x(dxa), edge_x(dxb)),
+                                     torch.minimum(edge_y(dya), edge_y(dyb)))
+                inside_rect = (dxa <= 0) & (dxb >= 0) & (dya <= 0) & (dyb >= 0)
+                mmin = torch.where(inside_rect, torch.zeros_like(mmin), mmin)
+                ov &= mmin <= thr_all[sel]
                 wl = blk[by.clamp(max=blk.shape[0] - 1), bx.clamp(max=blk.shape[1] - 1)]
                 total += int((inside & ov & (pos[sel] <= wl)).sum().item())
     return total

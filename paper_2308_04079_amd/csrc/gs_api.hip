@@ -36,6 +36,7 @@ Rules make_rules(const gs_config* cfg) {
   r.bg[2] = cfg->bg[2];
   r.isotropic = cfg->isotropic;
   r.grad_limit = cfg->grad_limit;
+  r.log_alpha_min = logf(cfg->alpha_min);
   return r;
 }
 

@@ -43,6 +43,7 @@ struct Rules {
   float bg[3];
   int32_t isotropic;   // Sigma = s^2 I, s = exp(mean log-scale)
   int32_t grad_limit;  // > 0: only the N front-most blended Gaussians get gradients
+  float log_alpha_min; // ln(alpha_min): below opacity o, alpha < alpha_min once m > 2 ln(o / alpha_min)
 };
 
 static_assert(sizeof(ProjViews) < 3000, "kernel argument block too large");

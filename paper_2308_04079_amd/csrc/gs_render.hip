@@ -11,7 +11,7 @@
 // The backward pass walks the same list back to front from the wave's last
 // contributor, recovers T by dividing the stored final T by (1 - alpha), and
 // reduces the nine per-pixel partial gradients of each Gaussian over the wave
-// with DPP before one lane issues the global atomics.
+// with lane exchanges before nine lanes issue the global atomics.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -83,13 +83,16 @@ __device__ __forceinline__ void tile_range(const uint32_t* __restrict__ ranges, 
   start = min(ranges[2 * tile], end);
 }
 
-// One list entry as gathered by a lane: kept if its 3-sigma ellipse can reach the
-// wave's block. Two tests, both exact supersets of the pixels with m <= ext^2:
-//  * the pixel box of the ellipse meets the block;
-//  * the second whitened coordinate e1 = w10 dx + w11 dy (m >= e1^2) is linear, so
-//    its extremes over the block are at the corner pixel centres: if |e1| > ext at
-//    all four with the same sign, no pixel of the block is inside. A relative slack
-//    of 1e-5 keeps the test conservative against FP32 rounding.
+// One list entry as gathered by a lane: kept if some pixel of the wave's block can
+// pass both per-pixel tests of the blend, m <= ext^2 and alpha >= alpha_min. With
+// alpha = min(alpha_max, o exp(-m/2)) the second holds only for m <= 2 ln(o / alpha_min),
+// so an entry is kept when the least m over the block is at most
+// min(ext^2, 2 ln(o / alpha_min)) (a superset of the contributing entries, so the
+// image and gradients do not change; faint Gaussians reach fewer blocks than their
+// 3-sigma box). The least m of the convex m(d) = |W d|^2 over the rectangle of the
+// block's pixel centres is 0 if the mean lies inside, else the least of its four edge
+// minima, each a parabola minimised at its vertex clamped to the edge. A slack far
+// above the FP32 rounding of both evaluations keeps the test conservative.
 struct Entry {
   float4 r0, r1, r2;
   uint32_t g, i;
@@ -97,18 +100,52 @@ struct Entry {
   bool keep;
 };
 
-__device__ __forceinline__ void gather_entry(const float* __restrict__ record,
-                                             const uint32_t* __restrict__ vals, uint32_t i,
-                                             bool in_range, const WaveTile& w, float ext, Entry& e) {
+__device__ __forceinline__ float edge_min_m(float w00, float w10, float w11, float X, float ylo,
+                                            float yhi, float i11) {
+  // d = (X, dy): e1 = w10 X + w11 dy vanishes at dy = -w10 X / w11
+  const float dy = fminf(fmaxf(-w10 * X * i11, ylo), yhi);
+  const float e0 = w00 * X, e1 = fmaf(w10, X, w11 * dy);
+  return fmaf(e0, e0, e1 * e1);
+}
+
+__device__ __forceinline__ float edge_min_m_y(float w00, float w10, float w11, float Y, float xlo,
+                                              float xhi, float iq) {
+  // d = (dx, Y): m = (w00^2 + w10^2) dx^2 + 2 w10 w11 Y dx + (w11 Y)^2, vertex at
+  // dx = -w10 w11 Y / (w00^2 + w10^2)
+  const float dx = fminf(fmaxf(-w10 * w11 * Y * iq, xlo), xhi);
+  const float e0 = w00 * dx, e1 = fmaf(w10, dx, w11 * Y);
+  return fmaf(e0, e0, e1 * e1);
+}
+
+__device__ __forceinline__ bool block_reachable(const float4& shape, float dxa, float dxb, float dya,
+                                                float dyb, const Rules& r) {
+  const float w00 = shape.x, w10 = shape.y, w11 = shape.z, o = shape.w;
+  const float thr = fminf(r.ext2, 2.0f * (__logf(o) - r.log_alpha_min));
+  const bool inside = dxa <= 0.0f && dxb >= 0.0f && dya <= 0.0f && dyb >= 0.0f;
+  const float i11 = __builtin_amdgcn_rcpf(w11), iq = __builtin_amdgcn_rcpf(fmaf(w00, w00, w10 * w10));
+  float mmin = fminf(fminf(edge_min_m(w00, w10, w11, dxa, dya, dyb, i11),
+                           edge_min_m(w00, w10, w11, dxb, dya, dyb, i11)),
+                     fminf(edge_min_m_y(w00, w10, w11, dya, dxa, dxb, iq),
+                           edge_min_m_y(w00, w10, w11, dyb, dxa, dxb, iq)));
+  mmin = inside ? 0.0f : mmin;
+  // size of the terms whose rounding enters m: |e0|, |e1| <= S over the rectangle
+  const float S = (fabsf(w00) + fabsf(w10)) * fmaxf(fabsf(dxa), fabsf(dxb)) +
+                  fabsf(w11) * fmaxf(fabsf(dya), fabsf(dyb));
+  const float slack = 1e-4f + S * (1e-4f + 1e-5f * S);
+  return mmin <= thr + slack;
+}
+
+__device__ __forceinline__ void gather_entry(const float* __restrict__ record, uint32_t g,
+                                             uint32_t i, const WaveTile& w, const Rules& rules,
+                                             Entry& e) {
   e.keep = false;
   e.i = i;
-  e.g = 0;
+  e.g = g;
   e.ilo = e.jlo = 0;
   e.r0 = make_float4(0, 0, 0, 0);
   e.r1 = e.r0;
   e.r2 = e.r0;
-  if (in_range) e.g = vals[i];
-  if (in_range && e.g < w.n_records) {
+  if (g < w.n_records) {
     const float4* rec = reinterpret_cast<const float4*>(record + (size_t)e.g * GS_RECORD_FLOATS);
     e.r0 = rec[0];
     const int lo = __float_as_int(e.r0.x), hi = __float_as_int(e.r0.y);
@@ -118,54 +155,69 @@ __device__ __forceinline__ void gather_entry(const float* __restrict__ record,
     e.keep = (e.ilo <= w.x1) && (ihi >= w.x0) && (e.jlo <= w.y1) && (jhi >= w.y0);
     if (e.keep) {
       e.r1 = rec[1];
+      // pixel centre minus mean at the block's edges, as the blend forms dx and dy
       const float mx = e.r0.z, my = e.r0.w;
       const float dxa = ((float)(w.x0 - e.ilo) + 0.5f) - mx, dxb = ((float)(w.x1 - e.ilo) + 0.5f) - mx;
       const float dya = ((float)(w.y0 - e.jlo) + 0.5f) - my, dyb = ((float)(w.y1 - e.jlo) + 0.5f) - my;
-      const float ea = fmaf(e.r1.y, dxa, e.r1.z * dya), eb = fmaf(e.r1.y, dxb, e.r1.z * dya);
-      const float ec = fmaf(e.r1.y, dxa, e.r1.z * dyb), ed = fmaf(e.r1.y, dxb, e.r1.z * dyb);
-      const float lim = ext * 1.00001f;
-      const float emin = fminf(fminf(ea, eb), fminf(ec, ed));
-      const float emax = fmaxf(fmaxf(ea, eb), fmaxf(ec, ed));
-      e.keep = !(emin > lim || emax < -lim);
+      e.keep = block_reachable(e.r1, dxa, dxb, dya, dyb, rules);
       if (e.keep) e.r2 = rec[2];
     }
   }
 }
 
 // Compact the kept entries of the wave into its LDS slice from slot `slot0` on, in
-// lane order; returns the new fill level.
+// lane order; returns the new fill level. The forward keeps the list position in
+// col.w; the backward (s_pos given) keeps the record index there, so that it arrives
+// with the colour for the atomics, and the position in s_pos.
 __device__ __forceinline__ int commit_entries(const Entry& e, int slot0, float4* s_geo,
-                                              float4* s_shape, float4* s_col, uint32_t* s_gid) {
+                                              float4* s_shape, float4* s_col, uint32_t* s_pos) {
   const uint64_t km = __ballot(e.keep);
   if (e.keep) {
     const int slot = slot0 + __popcll(km & lanemask_lt());
     s_geo[slot] = make_float4((float)e.ilo, (float)e.jlo, e.r0.z, e.r0.w);
     s_shape[slot] = e.r1;
-    s_col[slot] = make_float4(e.r2.x, e.r2.y, e.r2.z, __uint_as_float(e.i));
-    if (s_gid) s_gid[slot] = e.g;
+    s_col[slot] = make_float4(e.r2.x, e.r2.y, e.r2.z, __uint_as_float(s_pos ? e.g : e.i));
+    if (s_pos) s_pos[slot] = e.i;
   }
   return slot0 + __popcll(km);
 }
 
-// Stage the R * 64 consecutive list entries [first, first + 64 R), those at or below
-// `last_ok` only, into the wave's LDS slice (all gathers are issued before any
-// ballot). Returns the kept count.
+// Instance values (Gaussian record indices) of one batch, loaded one batch ahead so
+// that the first link of the gather chain (value, then record) is in flight while
+// the wave blends the previous batch. Entries past the batch's end hold ~0u, which
+// no record index reaches.
 template <int R>
-__device__ __forceinline__ int stage_batch(const float* __restrict__ record,
-                                           const uint32_t* __restrict__ vals, int64_t first,
-                                           int64_t last_ok, const WaveTile& w, float ext,
-                                           float4* s_geo, float4* s_shape, float4* s_col,
-                                           uint32_t* s_gid) {
-  Entry e[R];
+struct Ahead {
+  uint32_t g[R];
+};
+
+template <int R>
+__device__ __forceinline__ void load_ahead(const uint32_t* __restrict__ vals, int64_t first,
+                                           int64_t last_ok, Ahead<R>& a) {
   const int lane = threadIdx.x % kWave;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t i = first + r * kWave + lane;
-    gather_entry(record, vals, (uint32_t)i, i <= last_ok, w, ext, e[r]);
+    a.g[r] = (i <= last_ok) ? vals[i] : ~0u;
   }
+}
+
+// Stage the R * 64 consecutive list entries [first, first + 64 R) whose values `a`
+// holds into the wave's LDS slice (all gathers are issued before any ballot).
+// Returns the kept count.
+template <int R>
+__device__ __forceinline__ int stage_batch(const float* __restrict__ record, const Ahead<R>& a,
+                                           int64_t first, const WaveTile& w, const Rules& rules,
+                                           float4* s_geo, float4* s_shape, float4* s_col,
+                                           uint32_t* s_pos) {
+  Entry e[R];
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    gather_entry(record, a.g[r], (uint32_t)(first + r * kWave + lane), w, rules, e[r]);
   int cnt = 0;
 #pragma unroll
-  for (int r = 0; r < R; ++r) cnt = commit_entries(e[r], cnt, s_geo, s_shape, s_col, s_gid);
+  for (int r = 0; r < R; ++r) cnt = commit_entries(e[r], cnt, s_geo, s_shape, s_col, s_pos);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   return cnt;
@@ -191,10 +243,14 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int32_t last = -1;
   bool done = !w.inside;
+  Ahead<R> ahead;
+  load_ahead<R>(vals, start, (int64_t)end - 1, ahead);
   for (uint32_t base = start; base < end; base += BATCH) {
     if (__ballot(!done) == 0ull) break;
-    const int cnt = stage_batch<R>(record, vals, base, (int64_t)end - 1, w, rules.ext,
-                                   s_geo[wave], s_shape[wave], s_col[wave], nullptr);
+    const Ahead<R> cur = ahead;
+    const int cnt = stage_batch<R>(record, cur, base, w, rules, s_geo[wave], s_shape[wave],
+                                   s_col[wave], nullptr);
+    load_ahead<R>(vals, (int64_t)base + BATCH, (int64_t)end - 1, ahead);
     for (int k = 0; k < cnt; ++k) {
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
@@ -236,18 +292,23 @@ __device__ __forceinline__ int wave_max_int(int x) {
   return x;
 }
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_row(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
-                                                                0xF, 0xF, true));
+// Value of lane l ^ XM (XM < 16: a partner in the same 16-lane row) through ds_swizzle
+// (bit mode, and-mask 0x1F): the exchange runs in the LDS crossbar, beside the VALU
+// work of the other waves, where a DPP operand would occupy the VALU (measured ~3%
+// faster on the backward blend than row_mirror / row_half_mirror / quad_perm DPP).
+template <int XM>
+__device__ __forceinline__ float lane_xor(float x) {
+  static_assert(XM > 0 && XM < 16, "partner must be in the same row");
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), (XM << 10) | 0x1F));
 }
 
 // Wave sum of nine per-lane values as a reduce-scatter butterfly inside each 16-lane
-// DPP row: at every step a lane keeps half of its remaining values and adds its
-// partner's copy of them (9 -> 5 -> 3 -> 2 -> 1 registers). The mirror patterns
-// pair lanes that differ in all low bits, so they come first (split on bit 3, then
-// bit 2), then xor 2 and xor 1. Two cross-row exchanges finish the sum. In-row lane
-// l then holds the total of value kReduceIndex(l) when bit l of kReduceLanes is set.
+// row: at every step a lane keeps half of its remaining values and adds its partner's
+// copy of them (9 -> 5 -> 3 -> 2 -> 1 registers). The partners l ^ 15 and l ^ 7 differ
+// in all low bits, so they come first (split on bit 3, then bit 2), then l ^ 2 and
+// l ^ 1. Two cross-row exchanges finish the sum. In-row lane l then holds the total of
+// value reduce_index(l) when bit l of kReduceLanes is set.
 constexpr uint32_t kReduceLanes = 0x1737u;  // row lanes 0, 1, 2, 4, 5, 8, 9, 10, 12
 __device__ __forceinline__ int reduce_index(uint32_t l) {
   return 5 * ((l >> 3) & 1) + 3 * ((l >> 2) & 1) + 2 * ((l >> 1) & 1) + (l & 1);
@@ -258,17 +319,17 @@ __device__ __forceinline__ float wave_reduce9_scatter(float a0, float a1, float 
                                                       float a8) {
   const uint32_t l = __lane_id() & 15;
   const bool h3 = l & 8, h2 = l & 4, h1 = l & 2, h0 = l & 1;
-  const float x0 = (h3 ? a5 : a0) + dpp_row<0x140>(h3 ? a0 : a5);
-  const float x1 = (h3 ? a6 : a1) + dpp_row<0x140>(h3 ? a1 : a6);
-  const float x2 = (h3 ? a7 : a2) + dpp_row<0x140>(h3 ? a2 : a7);
-  const float x3 = (h3 ? a8 : a3) + dpp_row<0x140>(h3 ? a3 : a8);
-  const float x4 = (h3 ? 0.0f : a4) + dpp_row<0x140>(h3 ? a4 : 0.0f);
-  const float y0 = (h2 ? x3 : x0) + dpp_row<0x141>(h2 ? x0 : x3);
-  const float y1 = (h2 ? x4 : x1) + dpp_row<0x141>(h2 ? x1 : x4);
-  const float y2 = (h2 ? 0.0f : x2) + dpp_row<0x141>(h2 ? x2 : 0.0f);
-  const float z0 = (h1 ? y2 : y0) + dpp_row<0x4E>(h1 ? y0 : y2);
-  const float z1 = (h1 ? 0.0f : y1) + dpp_row<0x4E>(h1 ? y1 : 0.0f);
-  float v = (h0 ? z1 : z0) + dpp_row<0xB1>(h0 ? z0 : z1);
+  const float x0 = (h3 ? a5 : a0) + lane_xor<15>(h3 ? a0 : a5);
+  const float x1 = (h3 ? a6 : a1) + lane_xor<15>(h3 ? a1 : a6);
+  const float x2 = (h3 ? a7 : a2) + lane_xor<15>(h3 ? a2 : a7);
+  const float x3 = (h3 ? a8 : a3) + lane_xor<15>(h3 ? a3 : a8);
+  const float x4 = (h3 ? 0.0f : a4) + lane_xor<15>(h3 ? a4 : 0.0f);
+  const float y0 = (h2 ? x3 : x0) + lane_xor<7>(h2 ? x0 : x3);
+  const float y1 = (h2 ? x4 : x1) + lane_xor<7>(h2 ? x1 : x4);
+  const float y2 = (h2 ? 0.0f : x2) + lane_xor<7>(h2 ? x2 : 0.0f);
+  const float z0 = (h1 ? y2 : y0) + lane_xor<2>(h1 ? y0 : y2);
+  const float z1 = (h1 ? 0.0f : y1) + lane_xor<2>(h1 ? y1 : 0.0f);
+  float v = (h0 ? z1 : z0) + lane_xor<1>(h0 ? z0 : z1);
   v += __shfl_xor(v, 16, kWave);
   v += __shfl_xor(v, 32, kWave);
   return v;
@@ -286,7 +347,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   __shared__ float4 s_geo[WPT][BATCH];
   __shared__ float4 s_shape[WPT][BATCH];
   __shared__ float4 s_col[WPT][BATCH];
-  __shared__ uint32_t s_gid[WPT][BATCH];
+  __shared__ uint32_t s_pos[WPT][BATCH];
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -321,10 +382,12 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   if constexpr (LIMIT) {
     for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
       const int64_t bot = max((int64_t)start, top - (BATCH - 1));
-      const int cnt = stage_batch<R>(record, vals, bot, top, w, rules.ext, s_geo[wave],
-                                     s_shape[wave], s_col[wave], s_gid[wave]);
+      Ahead<R> cur;
+      load_ahead<R>(vals, bot, top, cur);
+      const int cnt = stage_batch<R>(record, cur, bot, w, rules, s_geo[wave], s_shape[wave],
+                                     s_col[wave], s_pos[wave]);
       for (int k = cnt - 1; k >= 0; --k) {
-        const int32_t pos = (int32_t)__float_as_uint(s_col[wave][k].w);
+        const int32_t pos = (int32_t)s_pos[wave][k];
         Eval e;
         eval_alpha(s_geo[wave][k], s_shape[wave][k], fpx, fpy, rules, e);
         n_blended += ((pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min)) ? 1 : 0;
@@ -332,15 +395,20 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       __builtin_amdgcn_wave_barrier();
     }
   }
+  Ahead<R> ahead;
+  load_ahead<R>(vals, max((int64_t)start, wave_last - (BATCH - 1)), wave_last, ahead);
   for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
     const int64_t bot = max((int64_t)start, top - (BATCH - 1));
-    const int cnt = stage_batch<R>(record, vals, bot, top, w, rules.ext, s_geo[wave],
-                                   s_shape[wave], s_col[wave], s_gid[wave]);
+    const Ahead<R> cur = ahead;
+    const int cnt = stage_batch<R>(record, cur, bot, w, rules, s_geo[wave], s_shape[wave],
+                                   s_col[wave], s_pos[wave]);
+    const int64_t ntop = top - BATCH;   // the next batch, [max(start, ntop - BATCH + 1), ntop]
+    load_ahead<R>(vals, max((int64_t)start, ntop - (BATCH - 1)), ntop, ahead);
     for (int k = cnt - 1; k >= 0; --k) {
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
       const float4 col = s_col[wave][k];
-      const int32_t pos = (int32_t)__float_as_uint(col.w);
+      const int32_t pos = (int32_t)s_pos[wave][k];
       Eval e;
       eval_alpha(geo, shape, fpx, fpy, rules, e);
       // branch-free: non-contributing lanes add zeros and keep their state
@@ -371,7 +439,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
         const float tot = wave_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g,
                                                d_b);
         if (atomic_lane)
-          atomicAdd(grad2d + (size_t)s_gid[wave][k] * GS_GRAD2D_FLOATS + atomic_slot, tot);
+          atomicAdd(grad2d + (size_t)__float_as_uint(col.w) * GS_GRAD2D_FLOATS + atomic_slot, tot);
       }
     }
     __builtin_amdgcn_wave_barrier();
