@@ -71,6 +71,10 @@ int fill_proj_views(const gs_camera* cams, int32_t n_views, int32_t tile, ProjVi
     out->cam[v].cy = cams[v].cy;
     out->cam[v].W = cams[v].width;
     out->cam[v].H = cams[v].height;
+    for (int k = 0; k < 3; ++k)
+      out->cam[v].C[k] = -((double)cams[v].R[0 * 3 + k] * cams[v].t[0] +
+                           (double)cams[v].R[1 * 3 + k] * cams[v].t[1] +
+                           (double)cams[v].R[2 * 3 + k] * cams[v].t[2]);
   }
   return GS_OK;
 }

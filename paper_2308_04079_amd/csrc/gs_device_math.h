@@ -79,16 +79,35 @@ __device__ __forceinline__ void sh_weighted_grad(float x, float y, float z, cons
   }
 }
 
+// 1/x, 1/sqrt(x) and sqrt(x) for finite x > 0: the hardware estimates (v_rcp_f64,
+// v_rsq_f64) refined by two Newton steps, within an ulp or two of the correctly rounded
+// value at a fraction of the IEEE sequences' cost. Every decision taken from these
+// values (pixel-box bounds, culls) has a margin many orders of magnitude wider. x = 0
+// gives inf or NaN, which the callers' culls reject as before.
+__device__ __forceinline__ double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  return y * fma(-hx * y, y, 1.5);
+}
+
+__device__ __forceinline__ double sqrt_d(double x) {
+  const double y = rsqrt_d(x);
+  const double s = x * y;
+  return fma(fma(-s, s, x), 0.5 * y, s);
+}
+
 // Unit view direction from the camera centre to the mean (FP64 difference, FP32 result).
-__device__ __forceinline__ float view_dir(const float* Rw, const float* tw, double x, double y,
-                                          double z, float* d) {
-  double cc[3];
-  for (int k = 0; k < 3; ++k)
-    cc[k] = -((double)Rw[0 * 3 + k] * tw[0] + (double)Rw[1 * 3 + k] * tw[1] +
-              (double)Rw[2 * 3 + k] * tw[2]);
-  const double ex = x - cc[0], ey = y - cc[1], ez = z - cc[2];
-  const double dist = sqrt(ex * ex + ey * ey + ez * ez);
-  const double idist = 1.0 / dist;
+__device__ __forceinline__ float view_dir(const Cam& cam, double x, double y, double z, float* d) {
+  const double ex = x - cam.C[0], ey = y - cam.C[1], ez = z - cam.C[2];
+  const double dist = sqrt_d(ex * ex + ey * ey + ez * ez);
+  const double idist = rcp_d(dist);
   d[0] = (float)(ex * idist);
   d[1] = (float)(ey * idist);
   d[2] = (float)(ez * idist);
@@ -161,7 +180,7 @@ __device__ __forceinline__ bool project_covariance(const Cam& cam, const Rules& 
                          (double)cam.R[r * 3 + 1] * M[1 * 3 + c2] +
                          (double)cam.R[r * 3 + 2] * M[2 * 3 + c2];
   const double fx = cam.fx, fy = cam.fy;
-  p.iz = 1.0 / p.tz;
+  p.iz = rcp_d(p.tz);
   const double J00 = fx * p.iz, J02 = -fx * p.tx * p.iz * p.iz;
   const double J11 = fy * p.iz, J12 = -fy * p.ty * p.iz * p.iz;
   for (int c2 = 0; c2 < 3; ++c2) {
@@ -190,7 +209,7 @@ __device__ __forceinline__ void project_geometry(const Cam& cam, const Rules& ru
   p.ok = isfinite(p.u) && isfinite(p.v);
   if (!p.ok) return;
   const double ext = (double)rules.ext;
-  const double rx = ext * sqrt(p.a), ry = ext * sqrt(p.c);
+  const double rx = ext * sqrt_d(p.a), ry = ext * sqrt_d(p.c);
   // pixel i is covered iff its centre i + 0.5 lies in [u - rx, u + rx]
   const double Wm1 = cam.W - 1, Hm1 = cam.H - 1;
   const double ilo = ceil_clamped(p.u - rx - 0.5, 0.0, Wm1 + 1.0);

@@ -12,6 +12,7 @@ constexpr int kWave = 64;
 
 // Per-view camera as the kernels see it (passed by value in the kernel arguments).
 struct Cam {
+  double C[3];   // camera centre -R^T t in world space (FP64, computed once per view)
   float R[9];
   float t[3];
   float fx, fy, cx, cy;
@@ -46,7 +47,7 @@ struct Rules {
   float log_alpha_min; // ln(alpha_min): below opacity o, alpha < alpha_min once m > 2 ln(o / alpha_min)
 };
 
-static_assert(sizeof(ProjViews) < 3000, "kernel argument block too large");
+static_assert(sizeof(ProjViews) < 3600, "kernel argument block too large");
 static_assert(sizeof(TileViews) < 1000, "kernel argument block too large");
 
 // host-side helpers (gs_api.cpp)

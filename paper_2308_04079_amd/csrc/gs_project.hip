@@ -76,7 +76,7 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
       ok = p.ok;
     }
     float d[3];
-    if (ok) ok = view_dir(cam.R, cam.t, x, y, z, d) > 0.0f;
+    if (ok) ok = view_dir(cam, x, y, z, d) > 0.0f;
     if (!ok) {
       tiles_touched[idx] = 0;
       continue;
@@ -91,7 +91,7 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
     const float z32 = (float)p.tz;
     depth_key[idx] = __float_as_uint(z32);
     // whitening L^-1 of Sigma' = L L^T: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
-    const double sa = sqrt(p.a), isa = 1.0 / sa, isd = 1.0 / sqrt(p.det);
+    const double sa = sqrt_d(p.a), isa = rcp_d(sa), isd = rsqrt_d(p.det);
     float4* rec = reinterpret_cast<float4*>(record + idx * GS_RECORD_FLOATS);
     rec[0] = make_float4(__int_as_float(p.i_lo | (p.j_lo << 16)), __int_as_float(p.i_hi | (p.j_hi << 16)),
                          (float)(p.u - p.i_lo), (float)(p.v - p.j_lo));
@@ -161,7 +161,7 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
       dop += gr[5];
       // whitening W = L^-1: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
       const double a = p.a, b = p.b, c = p.c;
-      const double sa = sqrt(a), isa = 1.0 / sa, isd = 1.0 / sqrt(p.det);
+      const double sa = sqrt_d(a), isa = rcp_d(sa), isd = rsqrt_d(p.det);
       const double isasd = isa * isd, idet = isd * isd, ia = isa * isa;
       const double gA = dw00 * (-0.5 * ia * isa) +
                         dw10 * (0.5 * b * ia * isasd + 0.5 * b * c * isasd * idet) +
@@ -252,7 +252,7 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
       if (tiles_touched[idx] <= 0) continue;
       const Cam& cam = views.cam[v];
       float d[3];
-      const float dist = view_dir(cam.R, cam.t, x, y, z, d);
+      const float dist = view_dir(cam, x, y, z, d);
       float Y[K];
       sh_basis<DEG>(d[0], d[1], d[2], Y);
       const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
