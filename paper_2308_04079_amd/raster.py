@@ -111,7 +111,7 @@ class RenderState:
         st, ct = ctypes.c_uint32(0), ctypes.c_uint32(0)
         inst = self.instances()
         _lib.lib().gs_read_status(ctypes.byref(inst), ctypes.byref(st), ctypes.byref(ct),
-                                  torch.cuda.current_stream().cuda_stream)
+                                  torch.cuda.current_stream(self.status.device).cuda_stream)
         return int(st.value), int(ct.value)
 
 

@@ -77,8 +77,9 @@ class Trainer:
     """Owns the parameters, the Adam moments and the density statistics."""
 
     def __init__(self, params: GaussianParams, cams, targets, extent: float,
-                 cfg: TrainConfig = TrainConfig(), max_sh_degree: int | None = None):
-        self.cfg = cfg
+                 cfg: TrainConfig | None = None, max_sh_degree: int | None = None):
+        self.cfg = cfg if cfg is not None else TrainConfig()
+        cfg = self.cfg
         self.params = params
         self.cams = list(cams)
         self.extent = float(extent)
