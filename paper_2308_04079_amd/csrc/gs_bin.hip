@@ -18,9 +18,10 @@ namespace gs {
 constexpr int kBinBlock = 256;
 constexpr int kBinItems = 16;                       // per thread
 constexpr int kBinTile = kBinBlock * kBinItems;     // 4096 per block
-// misc words: [0] visible pairs, [1] the same clamped to the capacity, [2..3] the
-// instance count summed over all pairs (64-bit), exact even when the capacity is short,
-// [4] the instances of the (clamped) depth-sorted pairs
+// misc words: [0] visible pairs, [1] the same clamped to the capacity, [4] the
+// instances of the (clamped) depth-sorted pairs. The exact instance count over all
+// pairs (64-bit, exact even when the capacity is short) is the sum of the per-block
+// parts in the workspace's tile_parts.
 constexpr int kMiscWords = 16;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -69,48 +70,74 @@ bin_init(uint32_t* __restrict__ misc) {
 }
 
 // VISIBLE: per block the number of visible pairs, and the block's instance count
-// added to the 64-bit total at instances_total. Otherwise per block the instance
-// count of the depth-sorted pairs, each pair's count also written densely in depth
-// order to sorted_counts.
+// (64-bit) in instances_part[block]. Otherwise per block the instance count of the
+// depth-sorted pairs, each pair's count also written densely in depth order to
+// sorted_counts.
 template <bool VISIBLE>
 __global__ void __launch_bounds__(kBinBlock)
 bin_block_sums(const int32_t* __restrict__ touched, const uint32_t* __restrict__ sorted,
                int64_t max_items,
                const uint32_t* __restrict__ n_items_dev, uint32_t* __restrict__ sums,
-               unsigned long long* __restrict__ instances_total,
+               unsigned long long* __restrict__ instances_part,
                uint32_t* __restrict__ sorted_counts) {
   __shared__ uint32_t s4[kBinBlock / kWave];
   const int64_t n_items = n_items_dev ? min((int64_t)n_items_dev[0], max_items) : max_items;
   const int64_t base = (int64_t)blockIdx.x * kBinTile;
-  uint32_t acc = 0, tiles = 0;
+  uint32_t acc = 0;
+  unsigned long long tiles = 0;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
     const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
     const uint32_t c = item_value<VISIBLE>(touched, sorted, i, n_items);
     acc += c;
-    if (VISIBLE && i < n_items) tiles += (uint32_t)max(touched[i], 0);
+    if (VISIBLE && i < n_items) tiles += (unsigned long long)max(touched[i], 0);
     if (!VISIBLE && i < n_items) sorted_counts[i] = c;
   }
   uint32_t tot;
   block_excl_scan(acc, s4, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
   if (VISIBLE) {
-    block_excl_scan(tiles, s4, &tot);
-    if (threadIdx.x == 0 && tot) atomicAdd(instances_total, (unsigned long long)tot);
+    // a per-block total, summed by the scan kernel, rather than one atomic per block on
+    // a single counter
+    __shared__ unsigned long long s_tiles[kBinBlock / kWave];
+    unsigned long long t = tiles;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) t += __shfl_xor(t, d, kWave);
+    if (__lane_id() == 0) s_tiles[threadIdx.x / kWave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long all = 0;
+#pragma unroll
+      for (int w = 0; w < kBinBlock / kWave; ++w) all += s_tiles[w];
+      instances_part[blockIdx.x] = all;
+    }
   }
 }
 
 // One block: exclusive scan of the block sums in place. Writes the total (and,
-// if clamped is given, the total clamped to `capacity`). With `exact` given, the
-// count written and checked against the capacity is *exact instead (the status
-// flag is raised when it exceeds the capacity).
+// if clamped is given, the total clamped to `capacity`). With `exact` given (n_exact
+// 64-bit per-block parts), the count written and checked against the capacity is
+// their sum instead (the status flag is raised when it exceeds the capacity).
 __global__ void __launch_bounds__(1024)
 bin_scan_sums(uint32_t* __restrict__ sums, int64_t n_blocks, int64_t capacity,
               uint32_t* __restrict__ total_out, uint32_t* __restrict__ clamped,
-              const unsigned long long* __restrict__ exact, uint32_t* __restrict__ status,
-              uint32_t* __restrict__ own_total) {
+              const unsigned long long* __restrict__ exact, int64_t n_exact,
+              uint32_t* __restrict__ status, uint32_t* __restrict__ own_total) {
   __shared__ uint64_t part[1024];
+  __shared__ uint64_t s_exact;
   const int t = threadIdx.x;
+  if (exact) {
+    uint64_t e = 0;
+    for (int64_t i = t; i < n_exact; i += 1024) e += exact[i];
+    part[t] = e;
+    __syncthreads();
+    for (int d = 512; d >= 1; d >>= 1) {
+      if (t < d) part[t] += part[t + d];
+      __syncthreads();
+    }
+    if (t == 0) s_exact = part[0];
+    __syncthreads();
+  }
   const int64_t per = (n_blocks + 1023) / 1024;
   const int64_t lo = (int64_t)t * per, hi = min(lo + per, n_blocks);
   uint64_t acc = 0;
@@ -130,7 +157,7 @@ bin_scan_sums(uint32_t* __restrict__ sums, int64_t n_blocks, int64_t capacity,
     run += s;
   }
   if (t == 1023) {
-    const uint64_t total = exact ? (uint64_t)exact[0] : part[1023];
+    const uint64_t total = exact ? s_exact : part[1023];
     total_out[0] = (uint32_t)min(total, (uint64_t)0xFFFFFFFFu);
     if (clamped) clamped[0] = (uint32_t)min(total, (uint64_t)capacity);
     if (status && total > (uint64_t)capacity) atomicOr(status, GS_STATUS_CAPACITY);
@@ -267,6 +294,7 @@ struct BinWs {
   uint32_t* exp_sums;
   uint32_t* offs;            // instance offset of every pair in depth order
   uint32_t* sorted_counts;   // tile count of every pair in depth order
+  unsigned long long* tile_parts;   // instance count of each 4096-pair block (index order)
   void* radix;
   size_t radix_bytes;
   int64_t nb;
@@ -280,7 +308,8 @@ static size_t bin_ws_layout(int64_t n_total, int db, BinWs* out, void* base) {
   const size_t w_sums = align_words((size_t)nb + 1);
   const size_t offs_off = align_words(w_misc + 2 * w_sums);
   const size_t scounts_off = align_words(offs_off + (size_t)n_total);
-  const size_t radix_off = align_words(scounts_off + (size_t)n_total);
+  const size_t parts_off = align_words(scounts_off + (size_t)n_total);
+  const size_t radix_off = align_words(parts_off + 2 * ((size_t)nb + 1));
   const size_t radix_bytes = radix_workspace_bytes(n_total, radix_passes(kDepthKeyBits, db));
   if (out) {
     uint32_t* p = static_cast<uint32_t*>(base);
@@ -289,6 +318,7 @@ static size_t bin_ws_layout(int64_t n_total, int db, BinWs* out, void* base) {
     out->exp_sums = p + w_misc + w_sums;
     out->offs = p + offs_off;
     out->sorted_counts = p + scounts_off;
+    out->tile_parts = reinterpret_cast<unsigned long long*>(p + parts_off);
     out->radix = p + radix_off;
     out->radix_bytes = radix_bytes;
     out->nb = nb;
@@ -329,14 +359,13 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
   const int db = cfg->sort_digit_bits;
   const InstanceBufs b =
       instance_bufs(inst, radix_passes(tile_key_bits(tv.tile_offset[n_views]), db));
-  unsigned long long* m_total = reinterpret_cast<unsigned long long*>(w.misc + 2);
   // 1. visible pairs in index order (and the exact instance count)
   bin_init<<<1, 64, 0, s>>>(w.misc);
   if (w.nb > 0)
     bin_block_sums<true><<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(
-        proj->tiles_touched, nullptr, total, nullptr, w.vis_sums, m_total, nullptr);
-  bin_scan_sums<<<1, 1024, 0, s>>>(w.vis_sums, w.nb, cap, w.misc, w.misc + 1, nullptr, nullptr,
-                                   nullptr);
+        proj->tiles_touched, nullptr, total, nullptr, w.vis_sums, w.tile_parts, nullptr);
+  bin_scan_sums<<<1, 1024, 0, s>>>(w.vis_sums, w.nb, cap, w.misc, w.misc + 1, nullptr, 0,
+                                   nullptr, nullptr);
   if (w.nb > 0)
     bin_compact<<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(
         proj->tiles_touched, proj->depth_key, total, w.vis_sums, cap, b.depth.keys[0],
@@ -352,8 +381,8 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
   if (nbe > 0)
     bin_block_sums<false><<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(
         proj->tiles_touched, sorted, max_vis, w.misc + 1, w.exp_sums, nullptr, w.sorted_counts);
-  bin_scan_sums<<<1, 1024, 0, s>>>(w.exp_sums, nbe, cap, inst->count, nullptr, m_total,
-                                   inst->status, w.misc + 4);
+  bin_scan_sums<<<1, 1024, 0, s>>>(w.exp_sums, nbe, cap, inst->count, nullptr, w.tile_parts,
+                                   w.nb, inst->status, w.misc + 4);
   // 4. the instances, front to back: pair offsets, then an output-partitioned expansion
   if (nbe > 0)
     bin_pair_offsets<<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(w.sorted_counts, w.misc + 1,
