@@ -16,7 +16,7 @@ from oracle.gaussians import project
 from oracle.raster import render_tiles, tile_lists
 from tests.gpu_common import GROUPS, TOL_GRAD, TOL_IMAGE, gpu_images, rel_l2, to_np
 from tests.test_gpu_fullsize import sample_tiles
-from tests.test_gpu_parity import check_ranges, expected_sorted_instances
+from tests.test_gpu_parity import check_ranges, check_tile_order, expected_sorted_instances
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,7 @@ def test_bench_sort_and_depth_keys_bit_exact(bench):
                           (ek >> np.uint64(32)).astype(np.int64))
     assert np.array_equal(to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF, ev)
     check_ranges(state, ek)
+    check_tile_order(state)
     tt = to_np(state.tiles_touched)
     dk = to_np(state.depth_key).view(np.uint32)
     for v, cam in enumerate(cams):

@@ -329,3 +329,20 @@ def test_blend_kernels_clip_ranges_and_tile_order_they_did_not_get_from_the_sort
     torch.cuda.synchronize()
     for k in GROUPS:
         assert np.isfinite(to_np(grads[k])).all(), k
+
+
+def check_tile_order(state):
+    """The issue order is a permutation of the tile ids, longest-list bucket first."""
+    order = to_np(state.order).astype(np.int64)
+    r = to_np(state.ranges).astype(np.int64).reshape(-1, 2)
+    assert np.array_equal(np.sort(order), np.arange(state.n_tiles))
+    lens = r[order, 1] - r[order, 0]
+    bucket = np.where(lens > 0, np.floor(np.log2(np.maximum(lens, 1))).astype(np.int64) + 1, 0)
+    assert np.all(np.diff(bucket) <= 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tile_order_is_longest_first(name):
+    sc, cams = CASES[name]
+    _, _, state = gpu_render(sc, cams)
+    check_tile_order(state)
