@@ -488,18 +488,26 @@ BWD_OPS_PER_EVAL = 48
 
 
 def cpu_baseline(log):
-    """The FP64 oracle timed on a bounded sample of one view of the same workload."""
-    import numpy as np
+    """The FP64 oracle timed on a bounded sample of one view of the same workload, with
+    NumPy's thread pools held to one thread (``cores`` = 1)."""
+    from threadpoolctl import threadpool_limits
 
     import scenes
-    from oracle.adjoint import blend_backward, empty_acc, project_backward
-    from oracle.gaussians import project
-    from oracle.raster import tile_lists, tile_pixels
     from oracle.rules import Rules
 
     sc = scenes.clustered_scene(3_000_000, 4, 3)
     cam = scenes.orbit_cameras(1, 4, resolutions=((1920, 1080),))[0]
     r = Rules()
+    with threadpool_limits(limits=1):       # BLAS and OpenMP pools: one thread
+        return _cpu_baseline_timed(sc, cam, r, log)
+
+
+def _cpu_baseline_timed(sc, cam, r, log):
+    import numpy as np
+
+    from oracle.adjoint import blend_backward, empty_acc, project_backward
+    from oracle.gaussians import project
+    from oracle.raster import tile_lists, tile_pixels
     t = time.perf_counter()
     p = project(sc, cam, r)
     t_proj = time.perf_counter() - t
