@@ -346,3 +346,44 @@ def test_tile_order_is_longest_first(name):
     sc, cams = CASES[name]
     _, _, state = gpu_render(sc, cams)
     check_tile_order(state)
+
+
+def test_the_largest_view_batch_equals_single_views():
+    """GS_MAX_VIEWS (32) views of mixed small sizes in one call of every stage give the
+    same images, transmittances and last contributors as 32 single-view calls."""
+    from paper_2308_04079_amd import _lib
+    sc = scenes.clustered_scene(5_000, 33, 1)
+    cams = scenes.orbit_cameras(32, 33, resolutions=((40, 24), (17, 33), (64, 16), (8, 8)))
+    assert len(cams) == 32 == _lib.MAX_VIEWS
+    _, _, batch = gpu_render(sc, cams)
+    bimgs = gpu_images(batch)
+    for v, cam in enumerate(cams):
+        _, _, single = gpu_render(sc, [cam])
+        s = gpu_images(single)[0]
+        for a, b in zip(bimgs[v], s):
+            np.testing.assert_array_equal(a, b)
+    compare_images(batch, sc, cams)
+
+
+def test_a_very_wide_image():
+    """A 32000 x 12 view (2000 x 1 tiles at 16 pixels, a ragged bottom row): tile lists,
+    image and transmittance against the oracle on sampled tiles."""
+    sc = scenes.uniform_scene(4000, 34, 1, (2.0, 8.0))
+    sc.means[0] *= 60.0                                   # spread along the image's width
+    sc.means[1] *= 0.05                                   # and close to its 12-pixel strip
+    cam = scenes.pinhole_camera(32000, 12, fov_y_deg=2.0)
+    _, _, state = gpu_render(sc, [cam])
+    ek, _ = expected_sorted_instances(state)
+    check_ranges(state, ek)
+    p = project(sc, cam)
+    tl = tile_lists(p)
+    lens = np.diff(tl.start)
+    nonempty = np.nonzero(lens > 0)[0]
+    assert nonempty.size > 20
+    tiles = np.unique(np.concatenate([nonempty[:: max(1, nonempty.size // 20)], [tl.tiles_x - 1]]))
+    img, T, gid = gpu_images(state)[0]
+    ref = render_tiles(p, tiles=tiles, tl=tl)
+    m = ref.done & ~ref.ambiguous
+    assert m.sum() > 1000
+    assert np.abs(img - ref.color)[m].max() <= TOL_IMAGE
+    np.testing.assert_allclose(T[m], ref.T_final[m], rtol=2e-3, atol=1e-6)
