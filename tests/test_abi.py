@@ -139,3 +139,15 @@ def test_loss_argument_checks(L):
     assert lib.gs_loss_photometric(1, 1, cc, 1, 1.5, 1, None, ws, 16, None) == L.ERR_ARG
     assert lib.gs_loss_photometric(1, 1, cc, 1, 0.2, 1, None, ws, 16, None) == L.ERR_ARG
     assert lib.gs_loss_photometric(None, 1, cc, 1, 0.2, 1, None, ws, 16, None) == L.ERR_ARG
+
+
+def test_a_missing_library_fails_loudly():
+    """No fallback: without the built library every entry raises."""
+    import subprocess
+    import sys
+    code = ("import pytest\nfrom paper_2308_04079_amd import _lib\n"
+            "with pytest.raises(RuntimeError, match='missing'):\n    _lib.lib()\nprint('raised')\n")
+    env = dict(os.environ, GS_LIBRARY=os.path.join(ROOT, "no_such_library.so"))
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 0 and "raised" in out.stdout, out.stderr
