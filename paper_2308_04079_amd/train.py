@@ -172,11 +172,15 @@ class Trainer:
                 float(b1), float(b2), float(cfg.eps), self.t, stream))
         for k, rate in lr.items():
             run(getattr(self.params, k), grads[k], getattr(self.m, k), getattr(self.v, k), rate)
-        # SH: the DC plane and the higher bands take different rates
+        # SH: the DC plane and the higher bands take different rates. Bands the ramp has
+        # not reached yet have zero gradients and still-zero moments, on which an Adam
+        # step changes nothing (m = v = 0, update 0 / eps = 0): they are skipped.
         sh, g = self.params.sh, grads["sh"]
         run(sh[0], g[0], self.m.sh[0], self.v.sh[0], cfg.lr_sh_dc)
-        if sh.shape[0] > 1:
-            run(sh[1:], g[1:], self.m.sh[1:], self.v.sh[1:], cfg.lr_sh_rest)
+        k_active = min(sh.shape[0], (self.sh_degree(it) + 1) ** 2)
+        if k_active > 1:
+            run(sh[1:k_active], g[1:k_active], self.m.sh[1:k_active], self.v.sh[1:k_active],
+                cfg.lr_sh_rest)
 
     def _densify(self, prune_large: bool):
         cfg = self.cfg

@@ -97,3 +97,28 @@ def test_training_loop_reduces_the_loss_and_densifies():
     assert len(set(counts)) > 1                         # density control changed the model
     assert tr.m.means.shape == tr.params.means.shape
     assert tr.sh_degree(tr.it) == 3
+
+
+def test_sh_bands_before_the_ramp_stay_untouched():
+    """Bands the SH ramp has not reached get no update and keep zero moments (the
+    Adam step on them is skipped, which equals running it on zero gradients)."""
+    import torch
+    from paper_2308_04079_amd import GaussianParams, Rasterizer
+    from paper_2308_04079_amd.train import TrainConfig, Trainer
+    sc = scenes.uniform_scene(2000, 35, sh_degree=3)
+    cams = [scenes.look_at_camera([0.2 * np.cos(a), 0.1, -0.5], [0, 0, 4.0], 96, 72)
+            for a in np.linspace(0, 2 * np.pi, 3, endpoint=False)]
+    r = Rasterizer(sh_degree=3)
+    tgt = GaussianParams.from_numpy(scenes.jitter_means(sc, 36, sd=0.05))
+    targets = [r.render(tgt, [c]).image.clone() for c in cams]
+    cfg = TrainConfig(iterations=30, views_per_step=1, warmup=(0, 0), sh_every=10,
+                      densify_from=1000, densify_until=999, reset_every=10 ** 6)
+    tr = Trainer(GaussianParams.from_numpy(sc), cams, targets, extent=2.0, cfg=cfg)
+    sh0 = tr.params.sh.clone()
+    for _ in range(15):                                   # degree 0 for 10 steps, then 1
+        tr.step()
+    torch.cuda.synchronize()
+    assert torch.equal(tr.params.sh[4:], sh0[4:])         # degrees 2 and 3 not reached
+    assert not torch.any(tr.m.sh[4:]) and not torch.any(tr.v.sh[4:])
+    assert not torch.equal(tr.params.sh[1:4], sh0[1:4])   # degree 1 active for 5 steps
+    assert not torch.equal(tr.params.sh[0], sh0[0])
