@@ -24,8 +24,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue rate without packed-FP32 instructions: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s.
 # FP32 vector peak in lane operations per second (an FMA counted once): the published
 # 157.3 TFLOP/s (an FMA counted as two flops) = 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.
 # The kernels reach VALU issue rates above the 16-lanes-per-SIMD figure, so the
@@ -428,7 +426,7 @@ def processed_pairs(st, cfg, T=16):
 def roofline(stages, state, count, n, V, cfg):
     """Roofline of the dominant kernel. For the blend kernels (VALU bound): lane
     evaluations actually issued (processed pairs x 64) x the arithmetic of one
-    evaluation, against the FP32 VALU issue rate."""
+    evaluation (FWD_OPS_PER_EVAL, BWD_OPS_PER_EVAL), against the FP32 VALU peak."""
     ms = stages["ms"]
     dom = max(("render_fwd", "render_bwd", "project", "project_bwd", "sort"), key=lambda k: ms[k])
     st = stages["state"]
@@ -481,10 +479,15 @@ def hbm_rates(ms, st, count, n, V, K, digit_bits):
 
 
 # FP32 VALU operations of one (pixel, Gaussian) evaluation as the method states it
-# (one op per add, mul, fma, compare, select, min, exp, reciprocal): the forward
-# evaluation is 22 ops, the backward one 48 (see the design doc for the itemisation).
+# (one op per add, mul, fma, compare, select, min, exp, reciprocal). Forward, 22:
+# offset 4, Mahalanobis 5, exp argument and exp 2, alpha 2, three tests 3, T' 2,
+# weight and colour accumulation 4. Backward, 57: the forward's 16 evaluation ops,
+# T recovery 3, colour gradient 4, alpha gradient 10, back-to-front accumulator 3,
+# clamp test 2, opacity / mean / whitening gradients 10, and the 9 adds that sum the
+# pixel's nine partial gradients into the Gaussian's totals (the accumulation the
+# forward's count includes for the colour).
 FWD_OPS_PER_EVAL = 22
-BWD_OPS_PER_EVAL = 48
+BWD_OPS_PER_EVAL = 57
 
 
 def cpu_baseline(log):
