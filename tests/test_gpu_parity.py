@@ -161,7 +161,10 @@ def backward_case(sc, cams, seed, tiles=None, **cfg):
 
 
 @pytest.mark.parametrize("name,cfg", [(n, {}) for n in CASES] +
-                         [("offcentre", {"lds_batch": 128}), ("ragged", {"tile_size": 32})])
+                         [("offcentre", {"lds_batch": 128}), ("ragged", {"tile_size": 32}),
+                          ("small", {"tile_size": 8}),
+                          ("offcentre", {"tile_size": 8, "lds_batch": 128}),
+                          ("ragged", {"tile_size": 32, "lds_batch": 128})])
 def test_backward_matches_oracle(name, cfg):
     sc, cams = CASES[name]
     grads, grad2d, gref, acc, p = backward_case(sc, cams, 5, **cfg)
