@@ -390,3 +390,23 @@ def test_a_very_wide_image():
     assert m.sum() > 1000
     assert np.abs(img - ref.color)[m].max() <= TOL_IMAGE
     np.testing.assert_allclose(T[m], ref.T_final[m], rtol=2e-3, atol=1e-6)
+
+
+def test_gaussians_larger_than_the_image():
+    """A few Gaussians whose 3-sigma boxes cover the whole view (clamped to it: every tile
+    lists them) among ordinary ones: sort, image and gradients against the oracle."""
+    sc = scenes.uniform_scene(600, 37, 1, (2.0, 6.0))
+    sc.log_scales[:, :5] = np.log(3.0)                    # 3 world units at depth 2-6
+    sc.opacity_logits[:5] = -3.0                          # faint, so the rest shows through
+    cams = [scenes.pinhole_camera(80, 56)]
+    _, _, state = gpu_render(sc, cams)
+    tt = to_np(state.tiles_touched)
+    assert (tt[:5] == 5 * 4).sum() >= 3                   # 80x56 at 16 px: 5 x 4 tiles
+    ek, ev = expected_sorted_instances(state)
+    M = int(to_np(state.count)[0])
+    assert np.array_equal(to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF, ev)
+    compare_images(state, sc, cams)
+    grads, grad2d, gref, acc, p = backward_case(sc, cams, 8)
+    for k in GROUPS:
+        a = to_np(grads[k]).astype(np.float64)
+        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
