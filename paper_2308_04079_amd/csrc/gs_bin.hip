@@ -3,11 +3,15 @@
 // front-to-back order, so that gs_sort only has to sort the instances by tile:
 //   1. compact the visible pairs (index order) with their depth keys;
 //   2. stable radix sort of (depth, index) (31 key bits: depth > 0);
-//   3. exclusive scan of the tile counts in depth order (the instance count and the
-//      capacity check come from an exact sum in step 1);
+//   3. per depth-sorted pair, one gather of its tile rectangle from the record (its
+//      tile count, first tile id and width, written densely in depth order), then
+//      the exclusive scan of the counts (the instance count and the capacity check
+//      come from an exact sum in step 1);
 //   4. expansion of every pair into its tiles, row-major, writing the global tile id
 //      and the pair's index, partitioned by output instance so every block does
-//      the same work (the nearest pairs cover the most tiles and sort first).
+//      the same work (the nearest pairs cover the most tiles and sort first); the
+//      offsets pass of step 3 records the pair each output block starts in, and the
+//      expansion reads only dense per-pair arrays.
 // The result is the paper's per-instance (tile | depth) key order once sorted by tile.
 #include <algorithm>
 
@@ -18,6 +22,7 @@ namespace gs {
 constexpr int kBinBlock = 256;
 constexpr int kBinItems = 16;                       // per thread
 constexpr int kBinTile = kBinBlock * kBinItems;     // 4096 per block
+constexpr int kExpandOut = 2048;                    // instances per expansion block
 // misc words: [0] visible pairs, [1] the same clamped to the capacity, [4] the
 // instances of the (clamped) depth-sorted pairs. The exact instance count over all
 // pairs (64-bit, exact even when the capacity is short) is the sum of the per-block
@@ -53,65 +58,104 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* smem4,
   return base + incl - x;
 }
 
-// Item i of the block's range: VISIBLE counts visible pairs (index order); otherwise
-// the tile count of the i-th pair in depth order.
-template <bool VISIBLE>
-__device__ __forceinline__ uint32_t item_value(const int32_t* __restrict__ touched,
-                                               const uint32_t* __restrict__ sorted, int64_t i,
-                                               int64_t n_items) {
-  if (i >= n_items) return 0u;
-  if (VISIBLE) return touched[i] > 0 ? 1u : 0u;
-  return (uint32_t)max(touched[sorted[i]], 0);
-}
-
 __global__ void __launch_bounds__(64)
 bin_init(uint32_t* __restrict__ misc) {
   if (threadIdx.x < kMiscWords) misc[threadIdx.x] = 0u;
 }
 
-// VISIBLE: per block the number of visible pairs, and the block's instance count
-// (64-bit) in instances_part[block]. Otherwise per block the instance count of the
-// depth-sorted pairs, each pair's count also written densely in depth order to
-// sorted_counts.
-template <bool VISIBLE>
+// Per block of the (view, Gaussian) pairs in index order: the number of visible pairs,
+// and the block's instance count (64-bit) in instances_part[block].
 __global__ void __launch_bounds__(kBinBlock)
-bin_block_sums(const int32_t* __restrict__ touched, const uint32_t* __restrict__ sorted,
-               int64_t max_items,
-               const uint32_t* __restrict__ n_items_dev, uint32_t* __restrict__ sums,
-               unsigned long long* __restrict__ instances_part,
-               uint32_t* __restrict__ sorted_counts) {
+bin_visible_sums(const int32_t* __restrict__ touched, int64_t n_items,
+                 uint32_t* __restrict__ sums, unsigned long long* __restrict__ instances_part) {
   __shared__ uint32_t s4[kBinBlock / kWave];
-  const int64_t n_items = n_items_dev ? min((int64_t)n_items_dev[0], max_items) : max_items;
+  __shared__ unsigned long long s_tiles[kBinBlock / kWave];
   const int64_t base = (int64_t)blockIdx.x * kBinTile;
   uint32_t acc = 0;
   unsigned long long tiles = 0;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
     const int64_t i = base + (int64_t)j * kBinBlock + threadIdx.x;
-    const uint32_t c = item_value<VISIBLE>(touched, sorted, i, n_items);
-    acc += c;
-    if (VISIBLE && i < n_items) tiles += (unsigned long long)max(touched[i], 0);
-    if (!VISIBLE && i < n_items) sorted_counts[i] = c;
+    const int32_t c = i < n_items ? touched[i] : 0;
+    acc += c > 0 ? 1u : 0u;
+    tiles += (unsigned long long)max(c, 0);
   }
   uint32_t tot;
   block_excl_scan(acc, s4, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-  if (VISIBLE) {
-    // a per-block total, summed by the scan kernel, rather than one atomic per block on
-    // a single counter
-    __shared__ unsigned long long s_tiles[kBinBlock / kWave];
-    unsigned long long t = tiles;
+  // a per-block total, summed by the scan kernel, rather than one atomic per block on
+  // a single counter
+  unsigned long long t = tiles;
 #pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) t += __shfl_xor(t, d, kWave);
-    if (__lane_id() == 0) s_tiles[threadIdx.x / kWave] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long all = 0;
+  for (int d = kWave / 2; d >= 1; d >>= 1) t += __shfl_xor(t, d, kWave);
+  if (__lane_id() == 0) s_tiles[threadIdx.x / kWave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long all = 0;
 #pragma unroll
-      for (int w = 0; w < kBinBlock / kWave; ++w) all += s_tiles[w];
-      instances_part[blockIdx.x] = all;
-    }
+    for (int w = 0; w < kBinBlock / kWave; ++w) all += s_tiles[w];
+    instances_part[blockIdx.x] = all;
   }
+}
+
+// Tile rectangle of a pair, from the pixel rectangle packed in its record: first
+// column and row, width and height, in tiles.
+struct TileRect {
+  uint32_t tx0, ty0, w, h;
+};
+
+__device__ __forceinline__ TileRect tile_rect(int2 lohi, int T) {
+  TileRect r;
+  r.tx0 = (uint32_t)((lohi.x & 0xFFFF) / T);
+  r.ty0 = (uint32_t)(((lohi.x >> 16) & 0xFFFF) / T);
+  r.w = (uint32_t)((lohi.y & 0xFFFF) / T) - r.tx0 + 1;
+  r.h = (uint32_t)(((lohi.y >> 16) & 0xFFFF) / T) - r.ty0 + 1;
+  return r;
+}
+
+__device__ __forceinline__ int view_of_pair(const TileViews& tv, uint32_t i, int64_t n) {
+  int v = 0;
+  while (v + 1 < tv.n_views && (int64_t)i >= (int64_t)(v + 1) * n) ++v;
+  return v;
+}
+
+// Per depth-sorted pair, from its record's pixel rectangle (the same rectangle whose
+// tile count the projection wrote to tiles_touched): width | height << 16 in tiles
+// (both at most 4096: 32767 pixels over tiles of 8 or more) and the global id of its
+// first tile, written densely in depth order; per block the instance count.
+__global__ void __launch_bounds__(kBinBlock)
+bin_pair_tiles(const uint32_t* __restrict__ sorted, const uint32_t* __restrict__ n_sorted_dev,
+               int64_t max_items, const float* __restrict__ record, int64_t n, TileViews tv,
+               uint32_t* __restrict__ sums, uint32_t* __restrict__ pair_wh,
+               uint32_t* __restrict__ pair_base) {
+  __shared__ uint32_t s4[kBinBlock / kWave];
+  const int64_t n_items = min((int64_t)n_sorted_dev[0], max_items);
+  const int64_t base = (int64_t)blockIdx.x * kBinTile;
+  uint32_t g[kBinItems];
+#pragma unroll
+  for (int j = 0; j < kBinItems; ++j) {
+    const int64_t s = base + (int64_t)j * kBinBlock + threadIdx.x;
+    g[j] = s < n_items ? sorted[s] : ~0u;
+  }
+  int2 lohi[kBinItems];
+#pragma unroll
+  for (int j = 0; j < kBinItems; ++j)
+    lohi[j] = g[j] != ~0u ? *reinterpret_cast<const int2*>(record + (int64_t)g[j] * GS_RECORD_FLOATS)
+                          : make_int2(0, 0);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < kBinItems; ++j) {
+    if (g[j] == ~0u) continue;
+    const int64_t s = base + (int64_t)j * kBinBlock + threadIdx.x;
+    const int v = view_of_pair(tv, g[j], n);
+    const TileRect r = tile_rect(lohi[j], tv.tile);
+    pair_wh[s] = r.w | (r.h << 16);
+    pair_base[s] = (uint32_t)tv.tile_offset[v] + r.ty0 * (uint32_t)tv.tiles_x[v] + r.tx0;
+    acc += r.w * r.h;
+  }
+  uint32_t tot;
+  block_excl_scan(acc, s4, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
 // One block: exclusive scan of the block sums in place. Writes the total (and,
@@ -208,83 +252,92 @@ bin_compact(const int32_t* __restrict__ touched, const uint32_t* __restrict__ de
 }
 
 // Start offset of every depth-sorted pair's instances: the block-local scan of the
-// tile counts plus the block's offset.
+// tile counts plus the block's offset. Every pair also records itself as the head of
+// each expansion block whose first output (a multiple of kExpandOut below n_out)
+// falls in its range, so that block needs no search for its first pair.
 __global__ void __launch_bounds__(kBinBlock)
-bin_pair_offsets(const uint32_t* __restrict__ sorted_counts,
+bin_pair_offsets(const uint32_t* __restrict__ pair_wh,
                  const uint32_t* __restrict__ n_sorted_dev, int64_t max_items,
-                 const uint32_t* __restrict__ block_offsets, uint32_t* __restrict__ offs) {
+                 const uint32_t* __restrict__ block_offsets, const uint32_t* __restrict__ n_out_dev,
+                 int64_t capacity, uint32_t* __restrict__ offs, uint32_t* __restrict__ heads) {
   __shared__ uint32_t s4[kBinBlock / kWave];
   const int64_t n_sorted = min((int64_t)n_sorted_dev[0], max_items);
+  const uint64_t n_out = (uint64_t)min((int64_t)n_out_dev[0], capacity);
   const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
   if ((int64_t)blockIdx.x * kBinTile >= n_sorted) return;   // uniform over the block
   uint32_t cnt[kBinItems], local = 0;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
     const int64_t s = base + j;
-    cnt[j] = s < n_sorted ? sorted_counts[s] : 0u;
+    const uint32_t wh = s < n_sorted ? pair_wh[s] : 0u;
+    cnt[j] = (wh & 0xFFFFu) * (wh >> 16);
     local += cnt[j];
   }
   uint32_t tot;
-  uint32_t run = block_offsets[blockIdx.x] + block_excl_scan(local, s4, &tot);
+  uint64_t run = (uint64_t)block_offsets[blockIdx.x] + block_excl_scan(local, s4, &tot);
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    if (base + j < n_sorted) offs[base + j] = run;
+    if (base + j < n_sorted) {
+      offs[base + j] = (uint32_t)run;
+      const uint64_t end = min(run + cnt[j], n_out);
+      for (uint64_t h = (run + kExpandOut - 1) / kExpandOut; h * kExpandOut < end; ++h)
+        heads[h] = (uint32_t)(base + j);
+    }
     run += cnt[j];
   }
 }
 
-// Expansion partitioned by output: block b writes instances [4096 b, 4096 b + 4096).
-// Its first pair is found by one binary search over the pair offsets; the (at most
-// 4097) pairs its range can touch are staged in LDS, and each output finds its pair
-// by binary search there. Every block does the same amount of work whatever the
-// tile counts (the nearest Gaussians cover the most tiles and sort first).
+// Expansion partitioned by output: block b writes instances [o0, o0 + kExpandOut),
+// o0 = kExpandOut b. Its pairs run from heads[b] to heads[b + 1] (the pair holding
+// the next block's first output), at most kExpandOut + 1 of them; they are staged in
+// LDS (offset, value, first tile id, width and tiles per row, all read densely), and
+// each output finds its pair by binary search over the staged offsets. Every block does the same amount of
+// work whatever the tile counts (the nearest Gaussians cover the most tiles and sort
+// first).
 __global__ void __launch_bounds__(kBinBlock)
 bin_expand(const uint32_t* __restrict__ sorted, const uint32_t* __restrict__ n_sorted_dev,
-           int64_t max_items, const float* __restrict__ record, int64_t n, TileViews tv,
-           const uint32_t* __restrict__ offs, const uint32_t* __restrict__ n_out_dev,
-           int64_t capacity, uint32_t* __restrict__ tiles, uint32_t* __restrict__ vals) {
-  __shared__ uint32_t s_off[kBinTile + 1];
-  __shared__ uint32_t s_slot[kBinTile + 1];
-  __shared__ int64_t s_first;
+           int64_t max_items, int64_t n, TileViews tv, const uint32_t* __restrict__ offs,
+           const uint32_t* __restrict__ pair_wh, const uint32_t* __restrict__ pair_base,
+           const uint32_t* __restrict__ heads,
+           const uint32_t* __restrict__ n_out_dev, int64_t capacity,
+           uint32_t* __restrict__ tiles, uint32_t* __restrict__ vals) {
+  constexpr int kStage = kExpandOut + 1;
+  __shared__ uint32_t s_off[kStage];
+  __shared__ uint32_t s_val[kStage];
+  __shared__ uint32_t s_base[kStage];   // global id of the pair's first tile
+  __shared__ uint32_t s_wx[kStage];     // rectangle width | tiles per row << 16
   const int64_t n_sorted = min((int64_t)n_sorted_dev[0], max_items);
   const int64_t n_out = min((int64_t)n_out_dev[0], capacity);
-  const int64_t o0 = (int64_t)blockIdx.x * kBinTile;
-  if (o0 >= n_out) return;   // uniform over the block
-  if (threadIdx.x == 0) {
-    // largest p with offs[p] <= o0 (offsets strictly increase: every pair has a tile)
-    int64_t lo = 0, hi = n_sorted - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if ((int64_t)offs[mid] <= o0) lo = mid; else hi = mid - 1;
-    }
-    s_first = lo;
+  const int64_t o0 = (int64_t)blockIdx.x * kExpandOut;
+  if (o0 >= n_out || n_sorted <= 0) return;   // uniform over the block
+  const int64_t o1 = min(o0 + kExpandOut, n_out);
+  const int64_t p0 = min((int64_t)heads[blockIdx.x], n_sorted - 1);
+  const int64_t p1 = o1 < n_out ? min((int64_t)heads[blockIdx.x + 1], n_sorted - 1) : n_sorted - 1;
+  // outputs [o0, o1) touch at most kExpandOut consecutive pairs from p0 on
+  const int n_pairs = (int)std::max<int64_t>(1, std::min<int64_t>(p1 - p0 + 1, kStage));
+  for (int j = threadIdx.x; j < n_pairs; j += kBinBlock) {
+    const uint32_t i = sorted[p0 + j];
+    const uint32_t tx = (uint32_t)tv.tiles_x[view_of_pair(tv, i, n)];
+    s_off[j] = offs[p0 + j];
+    s_val[j] = i;
+    s_base[j] = pair_base[p0 + j];
+    s_wx[j] = (pair_wh[p0 + j] & 0xFFFFu) | (tx << 16);
   }
   __syncthreads();
-  const int64_t p0 = s_first;
-  const int n_pairs = (int)min((int64_t)kBinTile + 1, n_sorted - p0);
-  for (int j = threadIdx.x; j < kBinTile + 1; j += kBinBlock) {
-    const bool ok = j < n_pairs;
-    s_off[j] = ok ? offs[p0 + j] : 0xFFFFFFFFu;
-    s_slot[j] = ok ? sorted[p0 + j] : 0u;
-  }
-  __syncthreads();
-  const int64_t o1 = min(o0 + kBinTile, n_out);
-  for (int64_t o = o0 + threadIdx.x; o < o1; o += kBinBlock) {
-    int lo = 0, hi = n_pairs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((int64_t)s_off[mid] <= o) lo = mid; else hi = mid - 1;
+#pragma unroll
+  for (int r = 0; r < kExpandOut / kBinBlock; ++r) {
+    const int64_t o = o0 + r * kBinBlock + threadIdx.x;
+    if (o < o1) {
+      int lo = 0, hi = n_pairs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)s_off[mid] <= o) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t k = (uint32_t)(o - (int64_t)s_off[lo]);
+      const uint32_t wx = s_wx[lo], wdt = wx & 0xFFFFu;
+      tiles[o] = s_base[lo] + (k / wdt) * (wx >> 16) + k % wdt;
+      vals[o] = s_val[lo];
     }
-    const uint32_t i = s_slot[lo];
-    const uint32_t k = (uint32_t)(o - (int64_t)s_off[lo]);
-    int v = 0;
-    while (v + 1 < tv.n_views && (int64_t)i >= (int64_t)(v + 1) * n) ++v;
-    const int2 lohi = *reinterpret_cast<const int2*>(record + (int64_t)i * GS_RECORD_FLOATS);
-    const int T = tv.tile;
-    const uint32_t tx0 = (uint32_t)((lohi.x & 0xFFFF) / T), ty0 = (uint32_t)(((lohi.x >> 16) & 0xFFFF) / T);
-    const uint32_t wdt = (uint32_t)((lohi.y & 0xFFFF) / T) - tx0 + 1;
-    tiles[o] = (uint32_t)tv.tile_offset[v] + (ty0 + k / wdt) * (uint32_t)tv.tiles_x[v] + tx0 + k % wdt;
-    vals[o] = i;
   }
 }
 
@@ -293,7 +346,7 @@ struct BinWs {
   uint32_t* vis_sums;
   uint32_t* exp_sums;
   uint32_t* offs;            // instance offset of every pair in depth order
-  uint32_t* sorted_counts;   // tile count of every pair in depth order
+  uint32_t* pair_wh;         // tile rectangle width | height << 16 of every pair in depth order
   unsigned long long* tile_parts;   // instance count of each 4096-pair block (index order)
   void* radix;
   size_t radix_bytes;
@@ -317,7 +370,7 @@ static size_t bin_ws_layout(int64_t n_total, int db, BinWs* out, void* base) {
     out->vis_sums = p + w_misc;
     out->exp_sums = p + w_misc + w_sums;
     out->offs = p + offs_off;
-    out->sorted_counts = p + scounts_off;
+    out->pair_wh = p + scounts_off;
     out->tile_parts = reinterpret_cast<unsigned long long*>(p + parts_off);
     out->radix = p + radix_off;
     out->radix_bytes = radix_bytes;
@@ -362,8 +415,8 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
   // 1. visible pairs in index order (and the exact instance count)
   bin_init<<<1, 64, 0, s>>>(w.misc);
   if (w.nb > 0)
-    bin_block_sums<true><<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(
-        proj->tiles_touched, nullptr, total, nullptr, w.vis_sums, w.tile_parts, nullptr);
+    bin_visible_sums<<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(proj->tiles_touched, total,
+                                                                w.vis_sums, w.tile_parts);
   bin_scan_sums<<<1, 1024, 0, s>>>(w.vis_sums, w.nb, cap, w.misc, w.misc + 1, nullptr, 0,
                                    nullptr, nullptr);
   if (w.nb > 0)
@@ -376,21 +429,30 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
                   inst->status, s);
   if (rc != GS_OK) return rc;
   const uint32_t* sorted = b.depth.vals[radix_passes(kDepthKeyBits, db) & 1];
-  // 3. tile counts in depth order -> instance offsets, count and capacity check
+  // 3. tile rectangles in depth order -> instance offsets, count and capacity check.
+  // The first tile ids and the block heads go to regions of the instance buffers that
+  // are dead once the depth sort is done: its first key array (max_vis <= capacity
+  // words) and its other value array (one word per kExpandOut outputs, at most
+  // capacity words). The expansion writes the tile sort's set 0 (keys_alt, vals or
+  // vals_alt), which overlaps neither.
+  const int depth_passes = radix_passes(kDepthKeyBits, db);
+  uint32_t* pair_base = b.depth.keys[0];
+  uint32_t* heads = b.depth.vals[(depth_passes + 1) & 1];
   const int64_t nbe = (max_vis + kBinTile - 1) / kBinTile;
   if (nbe > 0)
-    bin_block_sums<false><<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(
-        proj->tiles_touched, sorted, max_vis, w.misc + 1, w.exp_sums, nullptr, w.sorted_counts);
+    bin_pair_tiles<<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(
+        sorted, w.misc + 1, max_vis, proj->record, n, tv, w.exp_sums, w.pair_wh, pair_base);
   bin_scan_sums<<<1, 1024, 0, s>>>(w.exp_sums, nbe, cap, inst->count, nullptr, w.tile_parts,
                                    w.nb, inst->status, w.misc + 4);
-  // 4. the instances, front to back: pair offsets, then an output-partitioned expansion
+  // 4. the instances, front to back: pair offsets and block heads, then an
+  // output-partitioned expansion
   if (nbe > 0)
-    bin_pair_offsets<<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(w.sorted_counts, w.misc + 1,
-                                                              max_vis, w.exp_sums, w.offs);
-  const int64_t nbo = (cap + kBinTile - 1) / kBinTile;
+    bin_pair_offsets<<<dim3((unsigned)nbe), kBinBlock, 0, s>>>(
+        w.pair_wh, w.misc + 1, max_vis, w.exp_sums, w.misc + 4, cap, w.offs, heads);
+  const int64_t nbo = (cap + kExpandOut - 1) / kExpandOut;
   if (nbe > 0 && nbo > 0)
     bin_expand<<<dim3((unsigned)nbo), kBinBlock, 0, s>>>(
-        sorted, w.misc + 1, max_vis, proj->record, n, tv, w.offs, w.misc + 4, cap,
-        b.tiles.keys[0], b.tiles.vals[0]);
+        sorted, w.misc + 1, max_vis, n, tv, w.offs, w.pair_wh, pair_base, heads, w.misc + 4,
+        cap, b.tiles.keys[0], b.tiles.vals[0]);
   return launch_status();
 }
