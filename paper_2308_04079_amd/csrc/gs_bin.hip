@@ -251,6 +251,10 @@ bin_compact(const int32_t* __restrict__ touched, const uint32_t* __restrict__ de
   }
 }
 
+// LDS word of item i of a 4096-item block, padded by one word per 32 items so that
+// lanes reading 16 consecutive items each fall in different banks
+__device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
+
 // Start offset of every depth-sorted pair's instances: the block-local scan of the
 // tile counts plus the block's offset. Every pair also records itself as the head of
 // each expansion block whose first output (a multiple of kExpandOut below n_out)
@@ -260,30 +264,46 @@ bin_pair_offsets(const uint32_t* __restrict__ pair_wh,
                  const uint32_t* __restrict__ n_sorted_dev, int64_t max_items,
                  const uint32_t* __restrict__ block_offsets, const uint32_t* __restrict__ n_out_dev,
                  int64_t capacity, uint32_t* __restrict__ offs, uint32_t* __restrict__ heads) {
+  // the block's counts pass through LDS (one padded word per item) so that the global
+  // reads and writes are coalesced while each thread scans 16 consecutive items
+  __shared__ uint32_t s_t[kBinTile + kBinTile / 32];
   __shared__ uint32_t s4[kBinBlock / kWave];
   const int64_t n_sorted = min((int64_t)n_sorted_dev[0], max_items);
   const uint64_t n_out = (uint64_t)min((int64_t)n_out_dev[0], capacity);
-  const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
-  if ((int64_t)blockIdx.x * kBinTile >= n_sorted) return;   // uniform over the block
+  const int64_t blk = (int64_t)blockIdx.x * kBinTile;
+  if (blk >= n_sorted) return;   // uniform over the block
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    const int q = r * kBinBlock + threadIdx.x;
+    const uint32_t wh = blk + q < n_sorted ? pair_wh[blk + q] : 0u;
+    s_t[padded(q)] = (wh & 0xFFFFu) * (wh >> 16);
+  }
+  __syncthreads();
+  const int q0 = threadIdx.x * kBinItems;
   uint32_t cnt[kBinItems], local = 0;
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    const int64_t s = base + j;
-    const uint32_t wh = s < n_sorted ? pair_wh[s] : 0u;
-    cnt[j] = (wh & 0xFFFFu) * (wh >> 16);
+    cnt[j] = s_t[padded(q0 + j)];
     local += cnt[j];
   }
   uint32_t tot;
   uint64_t run = (uint64_t)block_offsets[blockIdx.x] + block_excl_scan(local, s4, &tot);
+  // each thread now overwrites only the 16 words it read: no barrier needed before
 #pragma unroll
   for (int j = 0; j < kBinItems; ++j) {
-    if (base + j < n_sorted) {
-      offs[base + j] = (uint32_t)run;
+    s_t[padded(q0 + j)] = (uint32_t)run;
+    if (blk + q0 + j < n_sorted) {
       const uint64_t end = min(run + cnt[j], n_out);
       for (uint64_t h = (run + kExpandOut - 1) / kExpandOut; h * kExpandOut < end; ++h)
-        heads[h] = (uint32_t)(base + j);
+        heads[h] = (uint32_t)(blk + q0 + j);
     }
     run += cnt[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    const int q = r * kBinBlock + threadIdx.x;
+    if (blk + q < n_sorted) offs[blk + q] = s_t[padded(q)];
   }
 }
 

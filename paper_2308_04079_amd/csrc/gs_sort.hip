@@ -29,9 +29,16 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
+// The histogram pass adds its block counts into one of kHistCopies copies, chosen by
+// block index: consecutive blocks are dispatched to different XCDs (eight on MI355X),
+// so each copy collects the atomics of one XCD instead of all blocks contending for
+// the same words; the scan kernel sums the copies.
+constexpr int kHistCopies = 8;
+constexpr int kHistWords = kMaxPasses * 256;
 
 struct RadixWs {
-  uint32_t* hist;      // [kMaxPasses][256] digit counts, then their exclusive scan
+  uint32_t* hist;      // [kHistCopies][kMaxPasses][256] digit counts; copy 0 then holds
+                       // the exclusive scan of their sum
   uint32_t* ticket;    // [kMaxPasses]
   uint32_t* lookback;  // [passes][n_blocks][256]
   int64_t n_blocks;
@@ -42,7 +49,7 @@ static int64_t radix_blocks(int64_t max_items) {
 }
 
 size_t radix_workspace_bytes(int64_t max_items, int passes) {
-  return (size_t)(kMaxPasses * 256 + 64 + (int64_t)passes * radix_blocks(max_items) * 256) *
+  return (size_t)(kHistCopies * kHistWords + 64 + (int64_t)passes * radix_blocks(max_items) * 256) *
          sizeof(uint32_t);
 }
 
@@ -51,7 +58,7 @@ static RadixWs carve(void* ws, int64_t max_items) {
   uint32_t* p = static_cast<uint32_t*>(ws);
   w.n_blocks = radix_blocks(max_items);
   w.hist = p;
-  w.ticket = p + kMaxPasses * 256;
+  w.ticket = p + kHistCopies * kHistWords;
   w.lookback = w.ticket + 64;
   return w;
 }
@@ -66,7 +73,7 @@ radix_init(RadixWs w, int passes, const uint32_t* __restrict__ count, int64_t ma
   const int64_t nb = (M + kSortTile - 1) / kSortTile;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = t0; i < (int64_t)kMaxPasses * 256; i += stride) w.hist[i] = 0;
+  for (int64_t i = t0; i < (int64_t)kHistCopies * kHistWords; i += stride) w.hist[i] = 0;
   for (int64_t i = t0; i < 64; i += stride) w.ticket[i] = 0;
   for (int p = 0; p < passes; ++p) {
     uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
@@ -74,6 +81,9 @@ radix_init(RadixWs w, int passes, const uint32_t* __restrict__ count, int64_t ma
   }
 }
 
+// Digit counts of every pass in one read of the keys: blocks take 4096-key tiles in
+// turn (sixteen loads in flight per thread), count in LDS, then add their counts to
+// their XCD's copy of the histogram.
 __global__ void __launch_bounds__(256)
 radix_histogram(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count,
                 int64_t max_items, int passes, int db, uint32_t* __restrict__ hist) {
@@ -82,14 +92,25 @@ radix_histogram(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ 
   __syncthreads();
   const int64_t M = item_count(count, max_items);
   const uint32_t mask = (1u << db) - 1;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
-    const uint32_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (p * db)) & mask], 1u);
+  for (int64_t base = (int64_t)blockIdx.x * kSortTile; base < M;
+       base += (int64_t)gridDim.x * kSortTile) {
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const int64_t i = base + (int64_t)r * 256 + threadIdx.x;
+      k[r] = i < M ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      if (base + (int64_t)r * 256 + threadIdx.x >= M) break;
+      for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k[r] >> (p * db)) & mask], 1u);
+    }
   }
   __syncthreads();
+  uint32_t* mine = hist + (size_t)(blockIdx.x % kHistCopies) * kHistWords;
   for (int i = threadIdx.x; i < passes * 256; i += 256) {
     const uint32_t c = (&sh[0][0])[i];
-    if (c) atomicAdd(&hist[i], c);
+    if (c) atomicAdd(&mine[i], c);
   }
 }
 
@@ -98,7 +119,9 @@ radix_scan_hist(uint32_t* __restrict__ hist, int passes) {
   __shared__ uint32_t s[256];
   const int t = threadIdx.x;
   for (int p = 0; p < passes; ++p) {
-    const uint32_t x = hist[p * 256 + t];
+    uint32_t x = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) x += hist[c * kHistWords + p * 256 + t];
     s[t] = x;
     __syncthreads();
     for (int d = 1; d < 256; d <<= 1) {
