@@ -23,7 +23,7 @@ namespace gs {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per block
-constexpr int kLookback = 16;                        // predecessors examined per step
+constexpr int kLookback = 8;                        // predecessors examined per step
 constexpr int kMaxPasses = 8;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
