@@ -348,27 +348,71 @@ sort_ranges(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ cou
 // longest bucket first (order inside a bucket is arbitrary; it changes no result).
 __device__ __forceinline__ int length_bucket(uint32_t len) { return len ? 32 - __clz(len) : 0; }
 
-__global__ void __launch_bounds__(1024)
-sort_tile_order(const uint32_t* __restrict__ ranges, int64_t n_tiles, uint32_t* __restrict__ order) {
-  __shared__ uint32_t cnt[33];
+// The order is built by blocks of 1024 tiles over the whole chip (a single block
+// serialises the LDS atomics of the few, crowded length buckets on one CU): each block
+// first writes its tiles' bucket counts as one row of a table in the workspace; then
+// bucket b starts after every tile of the longer buckets, the blocks follow one
+// another inside it, and LDS atomics hand out the positions inside a block.
+constexpr int kOrderBlock = 256;
+constexpr int kOrderItems = 4;
+constexpr int kOrderTiles = kOrderBlock * kOrderItems;
+constexpr int kBuckets = 33;
+
+static int64_t order_blocks(int64_t n_tiles) { return (n_tiles + kOrderTiles - 1) / kOrderTiles; }
+
+__device__ __forceinline__ int tile_bucket(const uint32_t* __restrict__ ranges, int64_t i) {
+  const uint2 r = reinterpret_cast<const uint2*>(ranges)[i];
+  return length_bucket(r.y - r.x);
+}
+
+__global__ void __launch_bounds__(kOrderBlock)
+sort_order_counts(const uint32_t* __restrict__ ranges, int64_t n_tiles, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t c[kBuckets];
   const int t = threadIdx.x;
-  if (t < 33) cnt[t] = 0;
+  if (t < kBuckets) c[t] = 0;
   __syncthreads();
-  for (int64_t i = t; i < n_tiles; i += 1024)
-    atomicAdd(&cnt[length_bucket(ranges[2 * i + 1] - ranges[2 * i])], 1u);
+  const int64_t base = (int64_t)blockIdx.x * kOrderTiles;
+#pragma unroll
+  for (int j = 0; j < kOrderItems; ++j) {
+    const int64_t i = base + j * kOrderBlock + t;
+    if (i < n_tiles) atomicAdd(&c[tile_bucket(ranges, i)], 1u);
+  }
   __syncthreads();
-  if (t == 0) {
-    uint32_t run = 0;
-    for (int b = 32; b >= 0; --b) {
-      const uint32_t c = cnt[b];
-      cnt[b] = run;
-      run += c;
+  if (t < kBuckets) counts[(int64_t)blockIdx.x * kBuckets + t] = c[t];
+}
+
+__global__ void __launch_bounds__(kOrderBlock)
+sort_order_place(const uint32_t* __restrict__ ranges, int64_t n_tiles,
+                 const uint32_t* __restrict__ counts, int n_blocks, uint32_t* __restrict__ order) {
+  __shared__ uint32_t total[kBuckets], before[kBuckets], cursor[kBuckets];
+  const int t = threadIdx.x;
+  if (t < kBuckets) total[t] = before[t] = 0;
+  __syncthreads();
+  // column sums of the table: over all blocks, and over the blocks before this one
+  const int n_entries = n_blocks * kBuckets;   // < 2^27: n_tiles < 2^31
+  const int mine = (int)blockIdx.x * kBuckets;
+  for (int e = t; e < n_entries; e += kOrderBlock) {
+    const uint32_t v = counts[e];
+    if (v) {
+      const int b = e % kBuckets;
+      atomicAdd(&total[b], v);
+      if (e < mine) atomicAdd(&before[b], v);
     }
   }
   __syncthreads();
-  for (int64_t i = t; i < n_tiles; i += 1024) {
-    const uint32_t pos = atomicAdd(&cnt[length_bucket(ranges[2 * i + 1] - ranges[2 * i])], 1u);
-    order[pos] = (uint32_t)i;
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int b = kBuckets - 1; b >= 0; --b) {
+      cursor[b] = run + before[b];
+      run += total[b];
+    }
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kOrderTiles;
+#pragma unroll
+  for (int j = 0; j < kOrderItems; ++j) {
+    const int64_t i = base + j * kOrderBlock + t;
+    if (i < n_tiles) order[atomicAdd(&cursor[tile_bucket(ranges, i)], 1u)] = (uint32_t)i;
   }
 }
 
@@ -392,6 +436,11 @@ InstanceBufs instance_bufs(const gs_instances* inst, int tile_passes) {
   return b;
 }
 
+// The tile-order count table follows the radix sort's workspace.
+static size_t order_table_offset(int64_t capacity, int passes) {
+  return (radix_workspace_bytes(capacity, passes) + 255) & ~(size_t)255;
+}
+
 }  // namespace gs
 
 using namespace gs;
@@ -402,7 +451,8 @@ extern "C" size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_tota
                                           const gs_config* cfg) {
   if (capacity < 0 || !cfg || check_config(cfg) != GS_OK) return 0;
   const int passes = radix_passes(tile_key_bits(n_tiles_total), cfg->sort_digit_bits);
-  return radix_workspace_bytes(capacity, passes);
+  return order_table_offset(capacity, passes) +
+         (size_t)std::max<int64_t>(0, order_blocks(n_tiles_total)) * kBuckets * sizeof(uint32_t);
 }
 
 extern "C" const uint32_t* gs_sorted_tile_ids(const gs_instances* inst, int64_t n_tiles_total,
@@ -435,6 +485,13 @@ extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs
   if (rc != GS_OK) return rc;
   sort_ranges<<<dim3((unsigned)((n_tiles_total + 255) / 256)), 256, 0, s>>>(
       b.sorted_tiles, inst->count, cap, n_tiles_total, tile_ranges);
-  if (tile_order) sort_tile_order<<<1, 1024, 0, s>>>(tile_ranges, n_tiles_total, tile_order);
+  if (tile_order) {
+    const int64_t nb = order_blocks(n_tiles_total);
+    uint32_t* table = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) +
+                                                  order_table_offset(cap, passes));
+    sort_order_counts<<<dim3((unsigned)nb), kOrderBlock, 0, s>>>(tile_ranges, n_tiles_total, table);
+    sort_order_place<<<dim3((unsigned)nb), kOrderBlock, 0, s>>>(tile_ranges, n_tiles_total, table,
+                                                               (int)nb, tile_order);
+  }
   return launch_status();
 }
