@@ -58,11 +58,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* smem4,
   return base + incl - x;
 }
 
-__global__ void __launch_bounds__(64)
-bin_init(uint32_t* __restrict__ misc) {
-  if (threadIdx.x < kMiscWords) misc[threadIdx.x] = 0u;
-}
-
 // Per block of the (view, Gaussian) pairs in index order: the number of visible pairs,
 // and the block's instance count (64-bit) in instances_part[block].
 __global__ void __launch_bounds__(kBinBlock)
@@ -432,8 +427,8 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
   const int db = cfg->sort_digit_bits;
   const InstanceBufs b =
       instance_bufs(inst, radix_passes(tile_key_bits(tv.tile_offset[n_views]), db));
-  // 1. visible pairs in index order (and the exact instance count)
-  bin_init<<<1, 64, 0, s>>>(w.misc);
+  // 1. visible pairs in index order (and the exact instance count); the scans write
+  // every misc word that is read later, so it needs no clearing
   if (w.nb > 0)
     bin_visible_sums<<<dim3((unsigned)w.nb), kBinBlock, 0, s>>>(proj->tiles_touched, total,
                                                                 w.vis_sums, w.tile_parts);
