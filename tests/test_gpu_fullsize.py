@@ -13,7 +13,7 @@ from oracle.adjoint import render_backward
 from oracle.gaussians import project
 from oracle.raster import render_tiles, tile_lists
 from tests.gpu_common import GROUPS, TOL_GRAD, TOL_IMAGE, gpu_images, gpu_render, rel_l2, to_np
-from tests.test_gpu_parity import check_ranges, expected_sorted_instances
+from tests.test_gpu_parity import check_ranges, check_tile_order, expected_sorted_instances
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +39,7 @@ def test_full_sort_bit_exact(full):
                           (ek >> np.uint64(32)).astype(np.int64))
     assert np.array_equal(to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF, ev)
     check_ranges(state, ek)
+    check_tile_order(state)            # 8160 tiles: eight blocks of the order kernels
     # depth keys of every visible Gaussian are the oracle's, bit for bit
     g_valid = to_np(state.tiles_touched)[:sc.n] > 0
     ok = g_valid & p.valid
