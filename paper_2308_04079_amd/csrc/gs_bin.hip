@@ -217,10 +217,19 @@ bin_compact(const int32_t* __restrict__ touched, const uint32_t* __restrict__ de
   const int64_t base = (int64_t)blockIdx.x * kBinTile;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   bool vis[kBinItems];
+  uint32_t key[kBinItems];
+  // every load of the block is issued before the first ballot (the depth keys of all
+  // items, visible or not: at a third visible, their lines are read anyway)
+  int32_t tc[kBinItems];
 #pragma unroll
   for (int r = 0; r < kBinItems; ++r) {
     const int64_t i = base + (int64_t)r * kBinBlock + threadIdx.x;
-    vis[r] = i < total_items && touched[i] > 0;
+    tc[r] = i < total_items ? touched[i] : 0;
+    key[r] = i < total_items ? depth_key[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kBinItems; ++r) {
+    vis[r] = tc[r] > 0;
     const uint64_t m = __ballot(vis[r]);
     if (lane == 0) s_wave[r][wave] = (uint32_t)__popcll(m);
   }
@@ -238,9 +247,8 @@ bin_compact(const int32_t* __restrict__ touched, const uint32_t* __restrict__ de
     const uint64_t m = __ballot(vis[r]);
     const uint32_t pos = run + before + (uint32_t)__popcll(m & below);
     if (vis[r] && (int64_t)pos < capacity) {
-      const int64_t i = base + (int64_t)r * kBinBlock + threadIdx.x;
-      keys[pos] = depth_key[i];
-      vals[pos] = (uint32_t)i;
+      keys[pos] = key[r];
+      vals[pos] = (uint32_t)(base + (int64_t)r * kBinBlock + threadIdx.x);
     }
     run += round;
   }
