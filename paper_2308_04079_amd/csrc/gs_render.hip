@@ -242,11 +242,14 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int32_t last = -1;
-  bool done = !w.inside;
+  // 1 while the pixel still blends, 0 once it stopped (or lies outside the image): a
+  // float, so that every decision below is a compare feeding one select, with no
+  // combining of lane masks
+  float live = w.inside ? 1.0f : 0.0f;
   Ahead<R> ahead;
   load_ahead<R>(vals, start, (int64_t)end - 1, ahead);
   for (uint32_t base = start; base < end; base += BATCH) {
-    if (__ballot(!done) == 0ull) break;
+    if (__ballot(live > 0.0f) == 0ull) break;
     const Ahead<R> cur = ahead;
     const int cnt = stage_batch<R>(record, cur, base, w, rules, s_geo[wave], s_shape[wave],
                                    s_col[wave], nullptr);
@@ -257,19 +260,23 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       const float4 col = s_col[wave][k];
       Eval e;
       eval_alpha(geo, shape, fpx, fpy, rules, e);
-      // branch-free: every lane evaluates, the decisions select what is kept
-      const bool take = !done && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min);
-      const float Tn = T * (1.0f - e.alpha);
-      const bool stop = take && (Tn < rules.T_min);
-      const bool blend = take && !stop;
-      const float wgt = blend ? T * e.alpha : 0.0f;
+      // branch-free: every lane evaluates. a is alpha where the Gaussian is taken (inside
+      // the extent, alpha >= alpha_min > 0, pixel live), else 0; an untaken entry then
+      // leaves T * (1 - 0) = T >= T_min, so only a taken one can stop the pixel
+      float a = (e.m <= rules.ext2) ? e.alpha : 0.0f;
+      a = (a >= rules.alpha_min) ? a : 0.0f;
+      a *= live;
+      const float Tn = T * (1.0f - a);
+      const bool stop = Tn < rules.T_min;
+      const float ab = stop ? 0.0f : a;   // alpha of a blended entry, else 0
+      const float wgt = T * ab;
       C0 = fmaf(wgt, col.x, C0);
       C1 = fmaf(wgt, col.y, C1);
       C2 = fmaf(wgt, col.z, C2);
-      T = blend ? Tn : T;
-      last = blend ? (int32_t)__float_as_uint(col.w) : last;
-      done = done || stop;
-      if ((k & 7) == 7 && __ballot(!done) == 0ull) break;
+      T = stop ? T : Tn;
+      last = (ab > 0.0f) ? (int32_t)__float_as_uint(col.w) : last;
+      live = stop ? 0.0f : live;
+      if ((k & 7) == 7 && __ballot(live > 0.0f) == 0ull) break;
     }
     __builtin_amdgcn_wave_barrier();
   }
