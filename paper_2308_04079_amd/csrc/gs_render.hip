@@ -254,7 +254,11 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
     const int cnt = stage_batch<R>(record, cur, base, w, rules, s_geo[wave], s_shape[wave],
                                    s_col[wave], nullptr);
     load_ahead<R>(vals, (int64_t)base + BATCH, (int64_t)end - 1, ahead);
-    for (int k = 0; k < cnt; ++k) {
+    // groups of 8 entries; the saturation ballot runs once per group
+    bool all_done = false;
+    for (int k0 = 0; k0 < cnt && !all_done; k0 += 8) {
+    const int kend = min(k0 + 8, cnt);
+    for (int k = k0; k < kend; ++k) {
       const float4 geo = s_geo[wave][k];
       const float4 shape = s_shape[wave][k];
       const float4 col = s_col[wave][k];
@@ -276,7 +280,8 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       T = stop ? T : Tn;
       last = (ab > 0.0f) ? (int32_t)__float_as_uint(col.w) : last;
       live = stop ? 0.0f : live;
-      if ((k & 7) == 7 && __ballot(live > 0.0f) == 0ull) break;
+    }
+    all_done = __ballot(live > 0.0f) == 0ull;
     }
     __builtin_amdgcn_wave_barrier();
   }
