@@ -22,7 +22,7 @@ import dataclasses
 
 import numpy as np
 
-from .rules import Rules
+from .rules import EPS32, Rules
 
 
 def sort_order(proj, mask=None) -> np.ndarray:
@@ -81,13 +81,42 @@ class BlendResult:
     last_id: np.ndarray    # (P,) Gaussian id of the last blended Gaussian, -1 if none
     n_eval: np.ndarray     # (P,) list entries evaluated (up to and including the stop)
     n_blend: np.ndarray    # (P,)
-    ambiguous: np.ndarray  # (P,) a decision lies within its margin
+    ambiguous: np.ndarray  # (P,) a decision that shapes the image lies within its margin
+    ambiguous_grad: np.ndarray  # (P,) ambiguous, or an alpha-clamp decision within its margin
+    T_err: np.ndarray      # (P,) bound on the relative FP32 rounding error of T_final
     steps: list | None     # per list entry, the forward state needed by the adjoint
+    flags: list | None     # per pixel, the (position, kind) of every decision within its margin
+
+
+# kinds of threshold decision, in the order an entry takes them
+DECIDE_EXTENT, DECIDE_ALPHA, DECIDE_STOP = 0, 1, 2
+
+
+def _whitening(proj, g):
+    """The whitening factor L^-1 = [[w00, 0], [w10, w11]] of Sigma' = L L^T (lower
+    Cholesky factor L), so that m = |L^-1 d|^2."""
+    a, b, c = proj.cov2d[g, 0, 0], proj.cov2d[g, 0, 1], proj.cov2d[g, 1, 1]
+    l00 = np.sqrt(a)
+    l10 = b / l00
+    l11 = np.sqrt(max(c - l10 * l10, 0.0))
+    return 1.0 / l00, -l10 / (l00 * l11), 1.0 / l11
+
+
+def _f32_gap(x: float) -> float:
+    """Distance between a threshold and its FP32 representation."""
+    return abs(float(np.float32(x)) - x)
 
 
 def blend(proj, ids: np.ndarray, px: np.ndarray, py: np.ndarray,
-          rules: Rules = Rules(), record: bool = False) -> BlendResult:
-    """BlendInOrder (Alg. 2) for the pixels (px, py) over the ordered Gaussian list ids."""
+          rules: Rules = Rules(), record: bool = False, forced=frozenset(),
+          flags: bool = False) -> BlendResult:
+    """BlendInOrder (Alg. 2) for the pixels (px, py) over the ordered Gaussian list ids.
+
+    ``forced`` holds (list position, decision kind) pairs whose decision is taken
+    the other way at every pixel of the call (the legitimate alternative outcomes
+    of a decision within its margin); ``flags`` records, per pixel, every decision
+    that lies within its margin.
+    """
     P = px.size
     cxp = px.astype(np.float64) + 0.5
     cyp = py.astype(np.float64) + 0.5
@@ -99,8 +128,14 @@ def blend(proj, ids: np.ndarray, px: np.ndarray, py: np.ndarray,
     n_eval = np.zeros(P, np.int64)
     n_blend = np.zeros(P, np.int64)
     amb = np.zeros(P, bool)
+    amb_grad = np.zeros(P, bool)
+    T_err = np.zeros(P)          # relative error bound of the running T
     ext2 = rules.sigma_extent ** 2
+    Km, Ka, Kt, eps = rules.margin_m, rules.margin_alpha, rules.margin_T, EPS32
+    gap_amin, gap_amax, gap_Tmin = (_f32_gap(rules.alpha_min), _f32_gap(rules.alpha_max),
+                                    _f32_gap(rules.T_min))
     steps = [] if record else None
+    flag_list = [[] for _ in range(P)] if flags else None
     for pos, g in enumerate(ids):
         active = ~done
         if not active.any():
@@ -110,30 +145,82 @@ def blend(proj, ids: np.ndarray, px: np.ndarray, py: np.ndarray,
         Q = proj.conic[g]
         m = Q[0, 0] * dx * dx + 2.0 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
         n_eval += active
-        amb |= active & (np.abs(m - ext2) < rules.margin_m * ext2)
-        inside = active & (m <= ext2)
+        # FP32 error bound of m evaluated as |L^-1 D + c|^2: D = pixel centre minus the
+        # centre of the box's corner pixel (exact), c = L^-1 (corner centre - mean) and
+        # L^-1 rounded to FP32, then two fused multiply-adds per component
+        w00, w10, w11 = _whitening(proj, g)
+        ax, ay = (proj.i_lo[g] + 0.5) - proj.u[g], (proj.j_lo[g] + 0.5) - proj.v[g]
+        c0, c1 = w00 * ax, w10 * ax + w11 * ay
+        Di = np.abs(px - proj.i_lo[g]).astype(np.float64)
+        Dj = np.abs(py - proj.j_lo[g]).astype(np.float64)
+        e0 = np.abs(w00 * dx)
+        e1 = np.sqrt(np.maximum(m - e0 * e0, 0.0))
+        inner = np.abs(w11 * (py - proj.j_lo[g]) + c1)
+        de0 = eps * (abs(w00) * Di + abs(c0) + e0)
+        de1 = eps * (abs(w10) * Di + abs(w11) * Dj + abs(c1) + inner + e1)
+        err_m = 2.0 * (e0 * de0 + e1 * de1) + eps * (e1 * e1 + m)
         G = np.exp(-0.5 * m)
         raw_alpha = proj.opacity[g] * G
+        clamped = raw_alpha > rules.alpha_max
         alpha = np.minimum(rules.alpha_max, raw_alpha)
-        amb |= inside & (np.abs(alpha - rules.alpha_min) < rules.margin_alpha * rules.alpha_min)
-        take = inside & (alpha >= rules.alpha_min)
+        rel_a = np.where(clamped, eps, 0.5 * err_m + eps * (m + 8.0))
+
+        flip = [(pos, k) in forced for k in (DECIDE_EXTENT, DECIDE_ALPHA, DECIDE_STOP)]
+        near_m = active & (np.abs(m - ext2) < Km * err_m)
+        inside = active & ((m <= ext2) != flip[0])
+        near_a = inside & (np.abs(alpha - rules.alpha_min) < Ka * (rel_a * alpha + gap_amin))
+        take = inside & ((alpha >= rules.alpha_min) != flip[1])
         Tn = T * (1.0 - alpha)
-        tol = (n_blend + 4) * rules.margin_T_per_step * rules.T_min
-        amb |= take & (np.abs(Tn - rules.T_min) < tol)
-        stop = take & (Tn < rules.T_min)
+        rel_Tn = T_err + alpha / (1.0 - alpha) * rel_a + 2.0 * eps
+        near_s = take & (np.abs(Tn - rules.T_min) < Kt * (rel_Tn * Tn + gap_Tmin))
+        stop = take & ((Tn < rules.T_min) != flip[2])
+        near_c = take & (np.abs(raw_alpha - rules.alpha_max) <
+                         Ka * ((0.5 * err_m + eps * (m + 8.0)) * raw_alpha + gap_amax))
+        amb |= near_m | near_a | near_s
+        amb_grad |= near_m | near_a | near_s | near_c
+        if flags:
+            for k, near in ((DECIDE_EXTENT, near_m), (DECIDE_ALPHA, near_a), (DECIDE_STOP, near_s)):
+                for p_ in np.nonzero(near)[0]:
+                    flag_list[p_].append((pos, k))
         done |= stop
         blended = take & ~stop
         if record:
-            steps.append((pos, g, blended.copy(), T.copy(), alpha, G, raw_alpha > rules.alpha_max,
-                          dx, dy))
+            steps.append((pos, g, blended.copy(), T.copy(), alpha, G, clamped, dx, dy))
         if blended.any():
             C[blended] += (T * alpha)[blended, None] * proj.rgb[g][None, :]
             T = np.where(blended, Tn, T)
+            T_err = np.where(blended, rel_Tn, T_err)
             last_pos[blended] = pos
             last_id[blended] = g
             n_blend += blended
     C += T[:, None] * np.asarray(rules.bg, dtype=np.float64)[None, :]
-    return BlendResult(C, T, last_pos, last_id, n_eval, n_blend, amb, steps)
+    return BlendResult(C, T, last_pos, last_id, n_eval, n_blend, amb, amb_grad, T_err, steps,
+                       flag_list)
+
+
+def pixel_outcomes(proj, ids: np.ndarray, x: int, y: int, rules: Rules = Rules(),
+                   limit: int = 64) -> list:
+    """Every legitimate outcome of one pixel: the blend with each combination of its
+    within-margin decisions taken either way (depth first, at most ``limit`` runs).
+
+    A decision ahead of every forced one is the same in every run, so each branch
+    only flips decisions that come after the last one it already forced.
+    """
+    px, py = np.array([x]), np.array([y])
+    out = []
+
+    def explore(forced: tuple):
+        r = blend(proj, ids, px, py, rules, forced=frozenset(forced), flags=True)
+        out.append(r)
+        after = forced[-1] if forced else (-1, -1)
+        for d in r.flags[0]:
+            if len(out) >= limit:
+                return
+            if d > after:
+                explore(forced + (d,))
+
+    explore(())
+    return out
 
 
 @dataclasses.dataclass
@@ -144,6 +231,8 @@ class Image:
     n_eval: np.ndarray      # (H, W)
     ambiguous: np.ndarray   # (H, W)
     done: np.ndarray        # (H, W) pixel was rendered by this call
+    ambiguous_grad: np.ndarray  # (H, W) ambiguous, or an alpha clamp within its margin
+    T_err: np.ndarray       # (H, W) relative FP32 error bound of T_final
 
 
 def render_bruteforce(proj, rules: Rules = Rules()) -> Image:
@@ -153,7 +242,8 @@ def render_bruteforce(proj, rules: Rules = Rules()) -> Image:
     py, px = np.divmod(np.arange(H * W), W)
     r = blend(proj, ids, px, py, rules)
     return Image(r.color.reshape(H, W, 3), r.T_final.reshape(H, W), r.last_id.reshape(H, W),
-                 r.n_eval.reshape(H, W), r.ambiguous.reshape(H, W), np.ones((H, W), bool))
+                 r.n_eval.reshape(H, W), r.ambiguous.reshape(H, W), np.ones((H, W), bool),
+                 r.ambiguous_grad.reshape(H, W), r.T_err.reshape(H, W))
 
 
 def tile_pixels(tile: int, tl: TileLists, width: int, height: int, T: int):
@@ -172,7 +262,8 @@ def render_tiles(proj, rules: Rules = Rules(), tiles=None, tl: TileLists | None 
     H, W = proj.height, proj.width
     tl = tile_lists(proj, rules) if tl is None else tl
     out = Image(np.zeros((H, W, 3)), np.ones((H, W)), np.full((H, W), -1, np.int64),
-                np.zeros((H, W), np.int64), np.zeros((H, W), bool), np.zeros((H, W), bool))
+                np.zeros((H, W), np.int64), np.zeros((H, W), bool), np.zeros((H, W), bool),
+                np.zeros((H, W), bool), np.zeros((H, W)))
     tiles = range(tl.tiles_x * tl.tiles_y) if tiles is None else tiles
     for t in tiles:
         px, py = tile_pixels(int(t), tl, W, H, rules.tile)
@@ -183,5 +274,7 @@ def render_tiles(proj, rules: Rules = Rules(), tiles=None, tl: TileLists | None 
         out.last_id[py, px] = r.last_id
         out.n_eval[py, px] = r.n_eval
         out.ambiguous[py, px] = r.ambiguous
+        out.ambiguous_grad[py, px] = r.ambiguous_grad
+        out.T_err[py, px] = r.T_err
         out.done[py, px] = True
     return out

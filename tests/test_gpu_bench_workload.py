@@ -14,7 +14,7 @@ import scenes
 from oracle.adjoint import render_backward
 from oracle.gaussians import project
 from oracle.raster import render_tiles, tile_lists
-from tests.gpu_common import GROUPS, TOL_GRAD, TOL_IMAGE, gpu_images, rel_l2, to_np
+from tests.gpu_common import GROUPS, check_grads, check_view_image, gpu_images, to_np
 from tests.test_gpu_fullsize import sample_tiles
 from tests.test_gpu_parity import check_ranges, check_tile_order, expected_sorted_instances
 
@@ -71,15 +71,8 @@ def test_bench_images_on_sampled_tiles(bench, v):
     p = project(sc, cams[v])
     tl = tile_lists(p)
     tiles = sample_tiles(tl, 32, 30 + v)
-    img, T, gid = gpu_images(state)[v]
     ref = render_tiles(p, tiles=tiles, tl=tl)
-    m = ref.done & ~ref.ambiguous
-    # these orbit views stack long lists near saturation, where the T' margin (it grows
-    # with the number of blends) flags about 0.1% of the pixels
-    assert ref.ambiguous[ref.done].mean() < 2e-3
-    assert np.abs(img - ref.color)[m].max() <= TOL_IMAGE
-    np.testing.assert_allclose(T[m], ref.T_final[m], rtol=2e-3, atol=1e-6)
-    assert np.array_equal(gid[m], ref.last_id[m])
+    print(check_view_image(gpu_images(state)[v], p, ref, tl))
 
 
 def test_bench_gradients_of_one_view(bench):
@@ -92,7 +85,7 @@ def test_bench_gradients_of_one_view(bench):
     tiles = sample_tiles(tl, 12, 40)
     ref = render_tiles(p, tiles=tiles, tl=tl)
     w = np.random.default_rng(41).standard_normal((cam.height, cam.width, 3))
-    w *= (ref.done & ~ref.ambiguous)[..., None]
+    w *= (ref.done & ~ref.ambiguous_grad)[..., None]
     dimg = torch.zeros_like(state.image)
     o = 3 * state.pix_offset[v]
     dimg[o:o + 3 * cam.width * cam.height] = torch.from_numpy(
@@ -100,6 +93,4 @@ def test_bench_gradients_of_one_view(bench):
     grads, _ = rast.backward(params, state, dimg)
     torch.cuda.synchronize()
     gref, _, _ = render_backward(sc, cam, w, tiles=tiles)
-    for k in GROUPS:
-        a = to_np(grads[k]).astype(np.float64)
-        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+    check_grads({k: to_np(grads[k]) for k in GROUPS}, gref)

@@ -1,6 +1,6 @@
 """Parity on the mixed-resolution batch: 1M Gaussians, SH degree 3, 16 orbit views of
 640x360 to 1920x1080 in one call per stage (54,000 global tiles, 16 tile-id bits). Sorted instances bit-exact in full; images on sampled
-tiles of several views; gradients of one view's sampled tiles with dL/dimage zero in
+tiles of several views (colour, T_final, last contributor); gradients of one view's sampled tiles with dL/dimage zero in
 every other view."""
 import numpy as np
 import pytest
@@ -9,7 +9,7 @@ import scenes
 from oracle.adjoint import render_backward
 from oracle.gaussians import project
 from oracle.raster import render_tiles, tile_lists
-from tests.gpu_common import GROUPS, TOL_GRAD, TOL_IMAGE, gpu_images, gpu_render, rel_l2, to_np
+from tests.gpu_common import GROUPS, check_grads, check_view_image, gpu_images, gpu_render, to_np
 from tests.test_gpu_fullsize import sample_tiles
 from tests.test_gpu_parity import check_ranges, expected_sorted_instances
 
@@ -45,12 +45,9 @@ def test_multiview_images_on_sampled_tiles(multi, v):
     p = project(sc, cams[v])
     tl = tile_lists(p)
     tiles = sample_tiles(tl, 16, 10 + v)
-    img, T, gid = gpu_images(state)[v]
     ref = render_tiles(p, tiles=tiles, tl=tl)
-    m = ref.done & ~ref.ambiguous
-    assert ref.ambiguous[ref.done].mean() < 1e-3
-    assert np.abs(img - ref.color)[m].max() <= TOL_IMAGE
-    assert np.array_equal(gid[m], ref.last_id[m])
+    # colour, T_final and last contributor; ambiguous pixels against their outcomes
+    print(check_view_image(gpu_images(state)[v], p, ref, tl))
 
 
 def test_multiview_gradients_of_one_view(multi):
@@ -63,7 +60,7 @@ def test_multiview_gradients_of_one_view(multi):
     tiles = sample_tiles(tl, 12, 20)
     ref = render_tiles(p, tiles=tiles, tl=tl)
     w = np.random.default_rng(21).standard_normal((cam.height, cam.width, 3))
-    w *= (ref.done & ~ref.ambiguous)[..., None]
+    w *= (ref.done & ~ref.ambiguous_grad)[..., None]
     dimg = torch.zeros_like(state.image)
     o = 3 * state.pix_offset[v]
     dimg[o:o + 3 * cam.width * cam.height] = torch.from_numpy(
@@ -71,9 +68,7 @@ def test_multiview_gradients_of_one_view(multi):
     grads, _ = rast.backward(params, state, dimg)
     torch.cuda.synchronize()
     gref, _, _ = render_backward(sc, cam, w, tiles=tiles)
-    for k in GROUPS:
-        a = to_np(grads[k]).astype(np.float64)
-        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+    check_grads({k: to_np(grads[k]) for k in GROUPS}, gref)
 
 
 @pytest.mark.parametrize("bits", [5, 6, 7])

@@ -2,7 +2,10 @@
 
 Bars: depth keys, pixel boxes, tile lists, sorted instances and tile ranges
 bit-exact (decisions within the oracle's margins excepted); images within 1e-4
-max-abs on unambiguous pixels; gradients within 1e-3 relative L2 per group.
+max-abs, T_final within its rounding bound and the same last contributor, where a
+pixel with a decision within its margin must equal one of its legitimate outcomes;
+gradients within 1e-3 relative L2 per group and element-wise within 1e-3 of the
+group's largest magnitude.
 """
 import math
 
@@ -14,8 +17,8 @@ from oracle.adjoint import render_backward
 from oracle.gaussians import project
 from oracle.raster import render_tiles, tile_lists
 from oracle.rules import Rules
-from tests.gpu_common import (GROUPS, TOL_GRAD, TOL_IMAGE, decode_records, gpu_images,
-                              gpu_render, rel_l2, to_np)
+from tests.gpu_common import (GROUPS, TOL_GRAD, TOL_IMAGE, check_grads, check_view_image,
+                              decode_records, gpu_images, gpu_render, rel_l2, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -115,16 +118,11 @@ def test_tile_lists_match_oracle(name):
 
 def compare_images(state, sc, cams, tiles=None, rules=Rules()):
     worst = 0.0
-    for v, (img, T, gid) in enumerate(gpu_images(state)):
+    for v, gpu in enumerate(gpu_images(state)):
         p = project(sc, cams[v], rules)
-        ref = render_tiles(p, rules, tiles=tiles)
-        m = ref.done & ~ref.ambiguous
-        assert ref.ambiguous[ref.done].mean() < 1e-3
-        err = np.abs(img - ref.color)[m]
-        worst = max(worst, float(err.max()) if err.size else 0.0)
-        assert worst <= TOL_IMAGE, (v, worst)
-        np.testing.assert_allclose(T[m], ref.T_final[m], rtol=2e-3, atol=1e-6)
-        assert np.array_equal(gid[m], ref.last_id[m])
+        tl = tile_lists(p, rules)
+        ref = render_tiles(p, rules, tiles=tiles, tl=tl)
+        worst = max(worst, check_view_image(gpu, p, ref, tl, rules)["worst"])
     return worst
 
 
@@ -152,7 +150,7 @@ def backward_case(sc, cams, seed, tiles=None, **cfg):
     cam = cams[0]
     ref = render_tiles(project(sc, cam), tiles=tiles)
     w = np.random.default_rng(seed).standard_normal((cam.height, cam.width, 3))
-    w *= (ref.done & ~ref.ambiguous)[..., None]
+    w *= (ref.done & ~ref.ambiguous_grad)[..., None]
     dimg = torch.from_numpy(np.ascontiguousarray(w.transpose(2, 0, 1)).astype(np.float32))
     grads, grad2d = rast.backward(params, state, dimg.reshape(-1).cuda())
     torch.cuda.synchronize()
@@ -170,13 +168,10 @@ def test_backward_matches_oracle(name, cfg):
     grads, grad2d, gref, acc, p = backward_case(sc, cams, 5, **cfg)
     g2 = to_np(grad2d).reshape(-1, 9)[:sc.n].astype(np.float64)
     ok = p.valid
-    assert rel_l2(g2[ok, 0], acc["u"][ok]) <= TOL_GRAD
-    assert rel_l2(g2[ok, 1], acc["v"][ok]) <= TOL_GRAD
-    assert rel_l2(g2[ok, 5], acc["opacity"][ok]) <= TOL_GRAD
-    assert rel_l2(g2[ok, 6:9], acc["rgb"][ok]) <= TOL_GRAD
-    for k in GROUPS:
-        a = to_np(grads[k]).astype(np.float64)
-        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+    check_grads({"u": g2[ok, 0], "v": g2[ok, 1], "opacity": g2[ok, 5], "rgb": g2[ok, 6:9]},
+                {"u": acc["u"][ok], "v": acc["v"][ok], "opacity": acc["opacity"][ok],
+                 "rgb": acc["rgb"][ok]}, ("u", "v", "opacity", "rgb"))
+    check_grads({k: to_np(grads[k]) for k in GROUPS}, gref)
 
 
 def test_single720_sampled_tiles_forward_and_backward():
@@ -187,9 +182,7 @@ def test_single720_sampled_tiles_forward_and_backward():
     _, _, state = gpu_render(sc, cams)
     compare_images(state, sc, cams, tiles=tiles)
     grads, _, gref, _, _ = backward_case(sc, cams, 6, tiles=tiles)
-    for k in GROUPS:
-        a = to_np(grads[k]).astype(np.float64)
-        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+    check_grads({k: to_np(grads[k]) for k in GROUPS}, gref)
 
 
 def test_multiview_batch_equals_single_views():
@@ -437,12 +430,9 @@ def test_a_very_wide_image():
     nonempty = np.nonzero(lens > 0)[0]
     assert nonempty.size > 20
     tiles = np.unique(np.concatenate([nonempty[:: max(1, nonempty.size // 20)], [tl.tiles_x - 1]]))
-    img, T, gid = gpu_images(state)[0]
     ref = render_tiles(p, tiles=tiles, tl=tl)
-    m = ref.done & ~ref.ambiguous
-    assert m.sum() > 1000
-    assert np.abs(img - ref.color)[m].max() <= TOL_IMAGE
-    np.testing.assert_allclose(T[m], ref.T_final[m], rtol=2e-3, atol=1e-6)
+    assert ref.done.sum() > 1000
+    check_view_image(gpu_images(state)[0], p, ref, tl)
 
 
 def test_gaussians_larger_than_the_image():
@@ -460,6 +450,4 @@ def test_gaussians_larger_than_the_image():
     assert np.array_equal(to_np(state.vals)[:M].astype(np.int64) & 0xFFFFFFFF, ev)
     compare_images(state, sc, cams)
     grads, grad2d, gref, acc, p = backward_case(sc, cams, 8)
-    for k in GROUPS:
-        a = to_np(grads[k]).astype(np.float64)
-        assert rel_l2(a, gref[k]) <= TOL_GRAD, (k, rel_l2(a, gref[k]))
+    check_grads({k: to_np(grads[k]) for k in GROUPS}, gref)
