@@ -57,7 +57,8 @@ typedef struct ihipStream_t* gs_stream_t; /* identical to hipStream_t */
 #define GS_MAX_DIM 32767       /* largest image width or height */
 #define GS_RECORD_FLOATS 12    /* floats per projected Gaussian record */
 #define GS_GRAD2D_FLOATS 9     /* floats per screen-space gradient record */
-#define GS_MAX_INSTANCES ((int64_t)1 << 30) /* largest instance capacity */
+#define GS_MAX_INSTANCES (((int64_t)1 << 30) - 1) /* largest instance capacity: the sort's
+                                                     look-back packs prefix counts in 30 bits */
 
 enum {
   GS_OK = 0,
@@ -124,9 +125,12 @@ typedef struct gs_params_grad { /* same layouts as gs_params; overwritten */
  *   record        GS_RECORD_FLOATS floats:
  *     [0] pixel box low corner  (i_lo | j_lo << 16) as int32 bits
  *     [1] pixel box high corner (i_hi | j_hi << 16) as int32 bits
- *     [2] u - i_lo, [3] v - j_lo   2D mean relative to the box corner
- *     [4] w00, [5] w10, [6] w11    L^-1 with Sigma' = L L^T (Cholesky), so
- *                                  m = (w00 dx)^2 + (w10 dx + w11 dy)^2
+ *     [2] c0, [3] c1               c = L^-1 ((i_lo + 0.5, j_lo + 0.5) - (u, v)), the
+ *                                  whitened offset of the box's corner pixel centre
+ *                                  from the 2D mean (u, v)
+ *     [4] w00, [5] w10, [6] w11    L^-1 = [[w00, 0], [w10, w11]] with Sigma' = L L^T
+ *                                  (Cholesky); the pixel (i_lo + Di, j_lo + Dj) has
+ *                                  m = (w00 Di + c0)^2 + (w10 Di + w11 Dj + c1)^2
  *     [7] opacity, [8..10] RGB colour, [11] camera depth (FP32)
  * Valid only where tiles_touched > 0. */
 typedef struct gs_projected {

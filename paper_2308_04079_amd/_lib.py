@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgs_mi355
 MAX_VIEWS = 32
 RECORD_FLOATS = 12
 GRAD2D_FLOATS = 9
-MAX_INSTANCES = 1 << 30
+MAX_INSTANCES = (1 << 30) - 1
 STATUS_CAPACITY = 1
 STATUS_SORT = 2
 

@@ -1,4 +1,5 @@
-"""Build libgs_mi355x.so (all HIP sources under csrc/) for gfx950, in-tree.
+"""Build libgs_mi355x.so (the HIP sources and the host-only C++ sources under csrc/) for
+gfx950, in-tree.
 
 Usage: python -m paper_2308_04079_amd.build  (or build() from Python).
 Every call recompiles. Flags:
@@ -38,9 +39,17 @@ def flags():
             "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
+def host_flags():
+    """Host-only C++ sources (the argument checks): no device code, no HIP headers."""
+    return ["-O2", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}"]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *flags(), "-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [hipcc(), *host_flags(), "-c", src, "-o", obj]
+    else:
+        cmd = [hipcc(), *flags(), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{res.stdout}\n{res.stderr}")
@@ -49,7 +58,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB_PATH + ".tmp"

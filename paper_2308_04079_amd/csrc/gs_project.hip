@@ -92,10 +92,15 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
     depth_key[idx] = __float_as_uint(z32);
     // whitening L^-1 of Sigma' = L L^T: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
     const double sa = sqrt_d(p.a), isa = rcp_d(sa), isd = rsqrt_d(p.det);
+    const double w00 = isa, w10 = -p.b * isa * isd, w11 = sa * isd;
+    // whitened offset of the box's corner pixel centre from the mean, c = L^-1 (p0 - mean):
+    // a pixel at p0 + D then has whitened offset L^-1 D + c, whose FP32 evaluation errs
+    // in proportion to the whitened terms, not to the pixel distance from the mean
+    const double ax = ((double)p.i_lo + 0.5) - p.u, ay = ((double)p.j_lo + 0.5) - p.v;
     float4* rec = reinterpret_cast<float4*>(record + idx * GS_RECORD_FLOATS);
     rec[0] = make_float4(__int_as_float(p.i_lo | (p.j_lo << 16)), __int_as_float(p.i_hi | (p.j_hi << 16)),
-                         (float)(p.u - p.i_lo), (float)(p.v - p.j_lo));
-    rec[1] = make_float4((float)isa, (float)(-p.b * isa * isd), (float)(sa * isd), (float)opac);
+                         (float)(w00 * ax), (float)(w10 * ax + w11 * ay));
+    rec[1] = make_float4((float)w00, (float)w10, (float)w11, (float)opac);
     rec[2] = make_float4(r, gc, b, z32);
   }
 }

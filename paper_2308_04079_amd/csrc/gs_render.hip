@@ -1,37 +1,45 @@
 // gs_render_fwd / gs_render_bwd: per-tile front-to-back blending (Alg. 2
 // BlendInOrder; Eq. front-to-back; App. C) and its back-to-front adjoint (Sec. 6).
 //
-// One workgroup per (view, tile); each 64-lane wave owns an 8x8 pixel block of
-// the tile and walks the tile's instance list on its own: it gathers 64 entries
-// (one per lane), keeps those whose 3-sigma pixel box meets its 8x8 block,
-// compacts them into its LDS slice with a ballot, and blends them from LDS
-// (broadcast reads). A wave stops as soon as all 64 of its pixels are saturated;
-// waves never wait for each other, so no workgroup barrier is needed.
+// One workgroup per (view, tile); each 64-lane wave owns an 8x8 pixel block of the
+// tile, and each 16-lane row of the wave a 4x4 block of that. A wave walks the tile's
+// instance list in rounds of 64 entries (one gathered per lane); each entry is tested
+// against the four 4x4 blocks of its rows and kept for a row only if some pixel of
+// that block can take it. Kept entries are compacted into the wave's LDS slice and
+// each row gets the list of its own entries; the rows then blend their lists side by
+// side, one entry per row per step (four Gaussians per wave instruction). Small
+// blocks follow the small footprints of typical Gaussians much more tightly than the
+// 8x8 block of a whole wave. Waves never wait for each other, so no workgroup
+// barrier is needed; a wave stops as soon as all 64 of its pixels are saturated.
 //
-// The backward pass walks the same list back to front from the wave's last
-// contributor, recovers T by dividing the stored final T by (1 - alpha), and
-// reduces the nine per-pixel partial gradients of each Gaussian over the wave
-// with lane exchanges before nine lanes issue the global atomics.
+// The backward pass walks the same lists back to front from each row's last
+// contributor, recovers T by dividing the stored final T by (1 - alpha), and sums
+// the nine per-pixel partial gradients of each row's Gaussian over the row's 16
+// lanes with lane exchanges before nine lanes per row issue the global atomics.
 #include <algorithm>
 
 #include "gs_internal.h"
 
 namespace gs {
 
-// Per-Gaussian LDS entry: geo = (box corner i_lo, j_lo as floats, mean - corner),
-// shape = (w00, w10, w11, opacity), col = (r, g, b, instance position bits).
+// Per-Gaussian LDS entry: geo = (centre of the box's corner pixel, whitened offset c of
+// that centre from the mean), shape = (w00, w10, w11, opacity), col = (r, g, b, list
+// position or record index), aux = (offset a of the mean from the corner centre, list
+// position; the backward only).
 struct Eval {
-  float dx, dy, e0, e1, m, G, alpha;
+  float di, dj, e0, e1, m, G, alpha;
 };
 
 // The one alpha evaluation used by both passes: identical instruction sequences
-// (the library is built with -ffp-contract=off), hence identical decisions.
+// (the library is built with -ffp-contract=off), hence identical decisions. The
+// pixel's offset D from the corner centre is exact (integers), and its whitened offset
+// from the mean is e = L^-1 D + c.
 __device__ __forceinline__ void eval_alpha(const float4& geo, const float4& shape, float fpx,
                                            float fpy, const Rules& r, Eval& e) {
-  e.dx = (fpx - geo.x) - geo.z;  // fpx - geo.x is exact: both are integers or half-integers
-  e.dy = (fpy - geo.y) - geo.w;
-  e.e0 = shape.x * e.dx;
-  e.e1 = fmaf(shape.y, e.dx, shape.z * e.dy);
+  e.di = fpx - geo.x;
+  e.dj = fpy - geo.y;
+  e.e0 = fmaf(shape.x, e.di, geo.z);
+  e.e1 = fmaf(shape.y, e.di, fmaf(shape.z, e.dj, geo.w));
   e.m = fmaf(e.e0, e.e0, e.e1 * e.e1);
   e.G = __expf(-0.5f * e.m);
   e.alpha = fminf(r.alpha_max, shape.w * e.G);
@@ -42,15 +50,19 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
 }
 
+constexpr int kRows = 4;       // 16-lane rows per wave, one 4x4 pixel block each
+constexpr int kRowLanes = 16;
+
 struct WaveTile {
-  int v, tile, W, H, x0, y0, x1, y1, px, py;
+  int v, tile, W, H, x0, y0, px, py, row;
   uint32_t n_records;
   bool inside;
 };
 
 // Workgroup b renders tile tile_order[b] when an order is given (gs_sort writes the
 // tiles longest list first, so the heaviest tiles start first and do not form the
-// tail of the launch), else tile b.
+// tail of the launch), else tile b. Row r of a wave owns the 4x4 block at
+// (x0 + 4 (r & 1), y0 + 4 (r >> 1)); lane l of the row its pixel (l & 3, l >> 2).
 template <int TS>
 __device__ __forceinline__ bool wave_tile(const TileViews& tv, const uint32_t* tile_order,
                                           WaveTile& w) {
@@ -67,10 +79,10 @@ __device__ __forceinline__ bool wave_tile(const TileViews& tv, const uint32_t* t
   w.x0 = tx * TS + (wave % WX) * 8;
   w.y0 = ty * TS + (wave / WX) * 8;
   if (w.x0 >= w.W || w.y0 >= w.H) return false;
-  w.x1 = min(w.x0 + 7, w.W - 1);
-  w.y1 = min(w.y0 + 7, w.H - 1);
-  w.px = w.x0 + (lane & 7);
-  w.py = w.y0 + (lane >> 3);
+  w.row = lane / kRowLanes;
+  const int l = lane % kRowLanes;
+  w.px = w.x0 + 4 * (w.row & 1) + (l & 3);
+  w.py = w.y0 + 4 * (w.row >> 1) + (l >> 2);
   w.inside = (w.px < w.W) && (w.py < w.H);
   return true;
 }
@@ -83,109 +95,193 @@ __device__ __forceinline__ void tile_range(const uint32_t* __restrict__ ranges, 
   start = min(ranges[2 * tile], end);
 }
 
-// One list entry as gathered by a lane: kept if some pixel of the wave's block can
-// pass both per-pixel tests of the blend, m <= ext^2 and alpha >= alpha_min. With
-// alpha = min(alpha_max, o exp(-m/2)) the second holds only for m <= 2 ln(o / alpha_min),
-// so an entry is kept when the least m over the block is at most
-// min(ext^2, 2 ln(o / alpha_min)) (a superset of the contributing entries, so the
-// image and gradients do not change; faint Gaussians reach fewer blocks than their
-// 3-sigma box). The least m of the convex m(d) = |W d|^2 over the rectangle of the
-// block's pixel centres is 0 if the mean lies inside, else the least of its four edge
-// minima, each a parabola minimised at its vertex clamped to the edge. A slack far
-// above the FP32 rounding of both evaluations keeps the test conservative.
+// One list entry as gathered by a lane: kept for row r if some pixel of the row's
+// 4x4 block can pass both per-pixel tests of the blend, m <= ext^2 and
+// alpha >= alpha_min. With alpha = min(alpha_max, o exp(-m/2)) the second holds only
+// for m <= 2 ln(o / alpha_min), so an entry is kept when the least m over the block is
+// at most min(ext^2, 2 ln(o / alpha_min)) (a superset of the contributing entries, so
+// the image and gradients do not change; faint Gaussians reach fewer blocks than their
+// 3-sigma box). Over the rectangle of the block's pixel-centre offsets D from the
+// corner centre, m = |L^-1 D + c|^2 is convex: its least value is 0 if the mean lies
+// inside, else the least of the four edge minima, each a parabola minimised at its
+// vertex clamped to the edge. A slack far above the FP32 rounding of both evaluations
+// keeps the test conservative.
 struct Entry {
   float4 r0, r1, r2;
   uint32_t g, i;
   int ilo, jlo;
-  bool keep;
+  float ax, ay;    // offset of the mean from the corner centre, a = -L c
+  uint32_t rows;   // bit r: kept for row r
 };
 
-__device__ __forceinline__ float edge_min_m(float w00, float w10, float w11, float X, float ylo,
-                                            float yhi, float i11) {
-  // d = (X, dy): e1 = w10 X + w11 dy vanishes at dy = -w10 X / w11
-  const float dy = fminf(fmaxf(-w10 * X * i11, ylo), yhi);
-  const float e0 = w00 * X, e1 = fmaf(w10, X, w11 * dy);
+struct Shape {
+  float w00, w10, w11, c0, c1, i11, iq;   // i11 = 1 / w11, iq = 1 / (w00^2 + w10^2)
+};
+
+__device__ __forceinline__ float edge_min_m(const Shape& s, float X, float ylo, float yhi) {
+  // D = (X, Dj): e1 = w11 Dj + (w10 X + c1) vanishes at Dj = -(w10 X + c1) / w11
+  const float b = fmaf(s.w10, X, s.c1);
+  const float dj = fminf(fmaxf(-b * s.i11, ylo), yhi);
+  const float e0 = fmaf(s.w00, X, s.c0), e1 = fmaf(s.w11, dj, b);
   return fmaf(e0, e0, e1 * e1);
 }
 
-__device__ __forceinline__ float edge_min_m_y(float w00, float w10, float w11, float Y, float xlo,
-                                              float xhi, float iq) {
-  // d = (dx, Y): m = (w00^2 + w10^2) dx^2 + 2 w10 w11 Y dx + (w11 Y)^2, vertex at
-  // dx = -w10 w11 Y / (w00^2 + w10^2)
-  const float dx = fminf(fmaxf(-w10 * w11 * Y * iq, xlo), xhi);
-  const float e0 = w00 * dx, e1 = fmaf(w10, dx, w11 * Y);
+__device__ __forceinline__ float edge_min_m_y(const Shape& s, float Y, float xlo, float xhi) {
+  // D = (Di, Y): m = (w00 Di + c0)^2 + (w10 Di + b)^2 with b = w11 Y + c1, vertex at
+  // Di = -(w00 c0 + w10 b) / (w00^2 + w10^2)
+  const float b = fmaf(s.w11, Y, s.c1);
+  const float di = fminf(fmaxf(-fmaf(s.w00, s.c0, s.w10 * b) * s.iq, xlo), xhi);
+  const float e0 = fmaf(s.w00, di, s.c0), e1 = fmaf(s.w10, di, b);
   return fmaf(e0, e0, e1 * e1);
 }
 
-__device__ __forceinline__ bool block_reachable(const float4& shape, float dxa, float dxb, float dya,
-                                                float dyb, const Rules& r) {
-  const float w00 = shape.x, w10 = shape.y, w11 = shape.z, o = shape.w;
-  const float thr = fminf(r.ext2, 2.0f * (__logf(o) - r.log_alpha_min));
-  const bool inside = dxa <= 0.0f && dxb >= 0.0f && dya <= 0.0f && dyb >= 0.0f;
-  const float i11 = __builtin_amdgcn_rcpf(w11), iq = __builtin_amdgcn_rcpf(fmaf(w00, w00, w10 * w10));
-  float mmin = fminf(fminf(edge_min_m(w00, w10, w11, dxa, dya, dyb, i11),
-                           edge_min_m(w00, w10, w11, dxb, dya, dyb, i11)),
-                     fminf(edge_min_m_y(w00, w10, w11, dya, dxa, dxb, iq),
-                           edge_min_m_y(w00, w10, w11, dyb, dxa, dxb, iq)));
+// Reachability test of one block (offset rectangle [xa, xb] x [ya, yb] from the corner
+// centre); thr = min(ext^2, 2 ln(o / alpha_min)).
+__device__ __forceinline__ bool block_reachable(const Shape& s, float thr, float ax, float ay,
+                                                float xa, float xb, float ya, float yb) {
+  const bool inside = ax >= xa && ax <= xb && ay >= ya && ay <= yb;
+  float mmin = fminf(fminf(edge_min_m(s, xa, ya, yb), edge_min_m(s, xb, ya, yb)),
+                     fminf(edge_min_m_y(s, ya, xa, xb), edge_min_m_y(s, yb, xa, xb)));
   mmin = inside ? 0.0f : mmin;
   // size of the terms whose rounding enters m: |e0|, |e1| <= S over the rectangle
-  const float S = (fabsf(w00) + fabsf(w10)) * fmaxf(fabsf(dxa), fabsf(dxb)) +
-                  fabsf(w11) * fmaxf(fabsf(dya), fabsf(dyb));
+  const float S = fabsf(s.c0) + fabsf(s.c1) + (fabsf(s.w00) + fabsf(s.w10)) * fmaxf(fabsf(xa), fabsf(xb)) +
+                  fabsf(s.w11) * fmaxf(fabsf(ya), fabsf(yb));
   const float slack = 1e-4f + S * (1e-4f + 1e-5f * S);
   return mmin <= thr + slack;
 }
 
+// Gather list entry i (record index g) and test it against the 4x4 blocks of the
+// wave's four rows. row_lim[r]: the last list position row r still needs (the
+// backward's row-wise last contributor; the forward's INT32_MAX while the row has a
+// live pixel, else -1).
 __device__ __forceinline__ void gather_entry(const float* __restrict__ record, uint32_t g,
                                              uint32_t i, const WaveTile& w, const Rules& rules,
-                                             Entry& e) {
-  e.keep = false;
+                                             const int32_t* row_lim, Entry& e) {
+  e.rows = 0;
   e.i = i;
   e.g = g;
   e.ilo = e.jlo = 0;
+  e.ax = e.ay = 0.0f;
   e.r0 = make_float4(0, 0, 0, 0);
   e.r1 = e.r0;
   e.r2 = e.r0;
-  if (g < w.n_records) {
-    const float4* rec = reinterpret_cast<const float4*>(record + (size_t)e.g * GS_RECORD_FLOATS);
-    e.r0 = rec[0];
-    const int lo = __float_as_int(e.r0.x), hi = __float_as_int(e.r0.y);
-    e.ilo = lo & 0xFFFF;
-    e.jlo = (lo >> 16) & 0xFFFF;
-    const int ihi = hi & 0xFFFF, jhi = (hi >> 16) & 0xFFFF;
-    e.keep = (e.ilo <= w.x1) && (ihi >= w.x0) && (e.jlo <= w.y1) && (jhi >= w.y0);
-    if (e.keep) {
-      e.r1 = rec[1];
-      // pixel centre minus mean at the block's edges, as the blend forms dx and dy
-      const float mx = e.r0.z, my = e.r0.w;
-      const float dxa = ((float)(w.x0 - e.ilo) + 0.5f) - mx, dxb = ((float)(w.x1 - e.ilo) + 0.5f) - mx;
-      const float dya = ((float)(w.y0 - e.jlo) + 0.5f) - my, dyb = ((float)(w.y1 - e.jlo) + 0.5f) - my;
-      e.keep = block_reachable(e.r1, dxa, dxb, dya, dyb, rules);
-      if (e.keep) e.r2 = rec[2];
+  if (g >= w.n_records) return;
+  const float4* rec = reinterpret_cast<const float4*>(record + (size_t)e.g * GS_RECORD_FLOATS);
+  e.r0 = rec[0];
+  const int lo = __float_as_int(e.r0.x), hi = __float_as_int(e.r0.y);
+  e.ilo = lo & 0xFFFF;
+  e.jlo = (lo >> 16) & 0xFFFF;
+  const int ihi = hi & 0xFFFF, jhi = (hi >> 16) & 0xFFFF;
+  const int qx1 = min(w.x0 + 7, w.W - 1), qy1 = min(w.y0 + 7, w.H - 1);
+  if (e.ilo > qx1 || ihi < w.x0 || e.jlo > qy1 || jhi < w.y0) return;
+  e.r1 = rec[1];
+  Shape sh;
+  sh.w00 = e.r1.x;
+  sh.w10 = e.r1.y;
+  sh.w11 = e.r1.z;
+  sh.c0 = e.r0.z;
+  sh.c1 = e.r0.w;
+  sh.i11 = __builtin_amdgcn_rcpf(sh.w11);
+  sh.iq = __builtin_amdgcn_rcpf(fmaf(sh.w00, sh.w00, sh.w10 * sh.w10));
+  // the mean's offset from the corner centre: L a = -c
+  e.ax = -sh.c0 * __builtin_amdgcn_rcpf(sh.w00);
+  e.ay = -fmaf(sh.w10, e.ax, sh.c1) * sh.i11;
+  const float thr = fminf(rules.ext2, 2.0f * (__logf(e.r1.w) - rules.log_alpha_min));
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int sx0 = w.x0 + 4 * (r & 1), sy0 = w.y0 + 4 * (r >> 1);
+    const int sx1 = min(sx0 + 3, w.W - 1), sy1 = min(sy0 + 3, w.H - 1);
+    // an empty block (past the image edge) has sx0 > sx1 or sy0 > sy1 and fails here
+    if ((int32_t)i > row_lim[r] || e.ilo > sx1 || ihi < sx0 || e.jlo > sy1 || jhi < sy0 ||
+        sx0 > sx1 || sy0 > sy1)
+      continue;
+    if (block_reachable(sh, thr, e.ax, e.ay, (float)(sx0 - e.ilo), (float)(sx1 - e.ilo),
+                        (float)(sy0 - e.jlo), (float)(sy1 - e.jlo)))
+      e.rows |= 1u << r;
+  }
+  if (e.rows) e.r2 = rec[2];
+}
+
+// LDS slice of one wave: the staged entries of a round (slot BATCH holds a null entry
+// that no pixel takes), and per row the slots of its entries in walk order, as bytes.
+template <int BATCH>
+struct WaveLds {
+  float4 geo[BATCH + 1];
+  float4 shape[BATCH + 1];
+  float4 col[BATCH + 1];
+  float4 aux[BATCH + 1];             // written and read by the backward only
+  uint32_t idx[kRows * BATCH / 4];   // row r's k-th slot: byte k of idx[r * BATCH / 4 ...]
+};
+
+// The null entry: zero shape and opacity give alpha = 0 < alpha_min at every pixel, and
+// its list position is past every last contributor.
+template <int BATCH>
+__device__ __forceinline__ void init_null_entry(WaveLds<BATCH>& s) {
+  if (__lane_id() == 0) {
+    s.geo[BATCH] = make_float4(0, 0, 0, 0);
+    s.shape[BATCH] = make_float4(0, 0, 0, 0);
+    s.col[BATCH] = make_float4(0, 0, 0, __uint_as_float(0xFFFFFFFFu));
+    s.aux[BATCH] = make_float4(0, 0, __uint_as_float(0x7FFFFFFFu), 0);
+  }
+}
+
+// Compact the kept entries of the wave into its LDS slice (slots in lane order) and
+// write every row's slot list: front to back (FWD) or back to front. Slots of a row
+// past its count point at the null entry. Returns the largest row count.
+template <int BATCH, int R, bool FWD>
+__device__ __forceinline__ int commit_round(const Entry* e, WaveLds<BATCH>& s, int& n_kept) {
+  constexpr uint32_t kNull = (uint32_t)BATCH * 0x01010101u;
+  const int lane = threadIdx.x % kWave;
+  for (int w = lane; w < kRows * BATCH / 4; w += kWave) s.idx[w] = kNull;
+  const uint64_t lt = lanemask_lt();
+  // all ballots first: each row's count of the round is then known, so the backward
+  // can write its list back to front directly
+  uint64_t km[R], br[R][kRows];
+  int cnt[kRows] = {0, 0, 0, 0};
+#pragma unroll
+  for (int sub = 0; sub < R; ++sub) {
+    km[sub] = __ballot(e[sub].rows != 0);
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      br[sub][r] = __ballot((e[sub].rows >> r) & 1u);
+      cnt[r] += __popcll(br[sub][r]);
     }
   }
-}
-
-// Compact the kept entries of the wave into its LDS slice from slot `slot0` on, in
-// lane order; returns the new fill level. The forward keeps the list position in
-// col.w; the backward (s_pos given) keeps the record index there, so that it arrives
-// with the colour for the atomics, and the position in s_pos.
-__device__ __forceinline__ int commit_entries(const Entry& e, int slot0, float4* s_geo,
-                                              float4* s_shape, float4* s_col, uint32_t* s_pos) {
-  const uint64_t km = __ballot(e.keep);
-  if (e.keep) {
-    const int slot = slot0 + __popcll(km & lanemask_lt());
-    s_geo[slot] = make_float4((float)e.ilo, (float)e.jlo, e.r0.z, e.r0.w);
-    s_shape[slot] = e.r1;
-    s_col[slot] = make_float4(e.r2.x, e.r2.y, e.r2.z, __uint_as_float(s_pos ? e.g : e.i));
-    if (s_pos) s_pos[slot] = e.i;
+  uint8_t* idx8 = reinterpret_cast<uint8_t*>(s.idx);
+  int slot0 = 0;
+  int before[kRows] = {0, 0, 0, 0};
+#pragma unroll
+  for (int sub = 0; sub < R; ++sub) {
+    const Entry& x = e[sub];
+    const int slot = slot0 + __popcll(km[sub] & lt);
+    if (x.rows) {
+      s.geo[slot] = make_float4((float)x.ilo + 0.5f, (float)x.jlo + 0.5f, x.r0.z, x.r0.w);
+      s.shape[slot] = x.r1;
+      // the forward keeps the list position in col.w; the backward keeps the record
+      // index there (it arrives with the colour, for the atomics), the position in aux
+      s.col[slot] = make_float4(x.r2.x, x.r2.y, x.r2.z, __uint_as_float(FWD ? x.i : x.g));
+      if (!FWD) s.aux[slot] = make_float4(x.ax, x.ay, __uint_as_float(x.i), 0.0f);
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      if ((x.rows >> r) & 1u) {
+        const int q = before[r] + __popcll(br[sub][r] & lt);   // rank in list order
+        idx8[r * BATCH + (FWD ? q : cnt[r] - 1 - q)] = (uint8_t)slot;
+      }
+      before[r] += __popcll(br[sub][r]);
+    }
+    slot0 += __popcll(km[sub]);
   }
-  return slot0 + __popcll(km);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  n_kept = slot0;
+  return max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
 }
 
-// Instance values (Gaussian record indices) of one batch, loaded one batch ahead so
-// that the first link of the gather chain (value, then record) is in flight while
-// the wave blends the previous batch. Entries past the batch's end hold ~0u, which
-// no record index reaches.
+// Instance values (Gaussian record indices) of one round, loaded one round ahead so
+// that the first link of the gather chain (value, then record) is in flight while the
+// wave blends the previous round. Entries past the round's end hold ~0u, which no
+// record index reaches.
 template <int R>
 struct Ahead {
   uint32_t g[R];
@@ -203,24 +299,25 @@ __device__ __forceinline__ void load_ahead(const uint32_t* __restrict__ vals, in
 }
 
 // Stage the R * 64 consecutive list entries [first, first + 64 R) whose values `a`
-// holds into the wave's LDS slice (all gathers are issued before any ballot).
-// Returns the kept count.
-template <int R>
-__device__ __forceinline__ int stage_batch(const float* __restrict__ record, const Ahead<R>& a,
+// holds (all gathers are issued before any ballot). Returns the largest row count;
+// n_kept receives the number of staged entries.
+template <int R, bool FWD>
+__device__ __forceinline__ int stage_round(const float* __restrict__ record, const Ahead<R>& a,
                                            int64_t first, const WaveTile& w, const Rules& rules,
-                                           float4* s_geo, float4* s_shape, float4* s_col,
-                                           uint32_t* s_pos) {
+                                           const int32_t* row_lim, WaveLds<R * kWave>& s,
+                                           int& n_kept) {
   Entry e[R];
   const int lane = threadIdx.x % kWave;
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    gather_entry(record, a.g[r], (uint32_t)(first + r * kWave + lane), w, rules, e[r]);
-  int cnt = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) cnt = commit_entries(e[r], cnt, s_geo, s_shape, s_col, s_pos);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  return cnt;
+    gather_entry(record, a.g[r], (uint32_t)(first + r * kWave + lane), w, rules, row_lim, e[r]);
+  return commit_round<R * kWave, R, FWD>(e, s, n_kept);
+}
+
+// Slot of this lane's row at step k (four steps per LDS word).
+template <int BATCH>
+__device__ __forceinline__ int row_slot(const WaveLds<BATCH>& s, int row, int k) {
+  return (s.idx[row * (BATCH / 4) + (k >> 2)] >> (8 * (k & 3))) & 0xFF;
 }
 
 template <int TS, int R>
@@ -231,12 +328,11 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
                   float* __restrict__ T_final, int32_t* __restrict__ last_idx) {
   constexpr int WPT = (TS / 8) * (TS / 8);
   constexpr int BATCH = R * kWave;
-  __shared__ float4 s_geo[WPT][BATCH];
-  __shared__ float4 s_shape[WPT][BATCH];
-  __shared__ float4 s_col[WPT][BATCH];
+  __shared__ WaveLds<BATCH> s_lds[WPT];
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
-  const int wave = threadIdx.x / kWave;
+  WaveLds<BATCH>& s = s_lds[threadIdx.x / kWave];
+  init_null_entry(s);
   uint32_t start, end;
   tile_range(ranges, w.tile, tv.n_inst, start, end);
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
@@ -249,39 +345,46 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   Ahead<R> ahead;
   load_ahead<R>(vals, start, (int64_t)end - 1, ahead);
   for (uint32_t base = start; base < end; base += BATCH) {
-    if (__ballot(live > 0.0f) == 0ull) break;
+    const uint64_t lv = __ballot(live > 0.0f);
+    if (lv == 0ull) break;
+    int32_t row_lim[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) row_lim[r] = ((lv >> (kRowLanes * r)) & 0xFFFFull) ? INT32_MAX : -1;
     const Ahead<R> cur = ahead;
-    const int cnt = stage_batch<R>(record, cur, base, w, rules, s_geo[wave], s_shape[wave],
-                                   s_col[wave], nullptr);
+    int n_kept;
+    const int n_steps = stage_round<R, true>(record, cur, base, w, rules, row_lim, s, n_kept);
     load_ahead<R>(vals, (int64_t)base + BATCH, (int64_t)end - 1, ahead);
-    // groups of 8 entries; the saturation ballot runs once per group
+    // groups of 8 steps; the saturation ballot runs once per group
     bool all_done = false;
-    for (int k0 = 0; k0 < cnt && !all_done; k0 += 8) {
-    const int kend = min(k0 + 8, cnt);
-    for (int k = k0; k < kend; ++k) {
-      const float4 geo = s_geo[wave][k];
-      const float4 shape = s_shape[wave][k];
-      const float4 col = s_col[wave][k];
-      Eval e;
-      eval_alpha(geo, shape, fpx, fpy, rules, e);
-      // branch-free: every lane evaluates. a is alpha where the Gaussian is taken (inside
-      // the extent, alpha >= alpha_min > 0, pixel live), else 0; an untaken entry then
-      // leaves T * (1 - 0) = T >= T_min, so only a taken one can stop the pixel
-      float a = (e.m <= rules.ext2) ? e.alpha : 0.0f;
-      a = (a >= rules.alpha_min) ? a : 0.0f;
-      a *= live;
-      const float Tn = T * (1.0f - a);
-      const bool stop = Tn < rules.T_min;
-      const float ab = stop ? 0.0f : a;   // alpha of a blended entry, else 0
-      const float wgt = T * ab;
-      C0 = fmaf(wgt, col.x, C0);
-      C1 = fmaf(wgt, col.y, C1);
-      C2 = fmaf(wgt, col.z, C2);
-      T = stop ? T : Tn;
-      last = (ab > 0.0f) ? (int32_t)__float_as_uint(col.w) : last;
-      live = stop ? 0.0f : live;
-    }
-    all_done = __ballot(live > 0.0f) == 0ull;
+    for (int k0 = 0; k0 < n_steps && !all_done; k0 += 8) {
+      const int kend = min(k0 + 8, n_steps);
+      uint32_t word = 0;
+      for (int k = k0; k < kend; ++k) {
+        if ((k & 3) == 0) word = s.idx[w.row * (BATCH / 4) + (k >> 2)];   // four steps' slots
+        const int slot = (word >> (8 * (k & 3))) & 0xFF;
+        const float4 geo = s.geo[slot];
+        const float4 shape = s.shape[slot];
+        const float4 col = s.col[slot];
+        Eval e;
+        eval_alpha(geo, shape, fpx, fpy, rules, e);
+        // branch-free: every lane evaluates. a is alpha where the Gaussian is taken
+        // (inside the extent, alpha >= alpha_min > 0, pixel live), else 0; an untaken
+        // entry then leaves T * (1 - 0) = T >= T_min, so only a taken one can stop
+        float a = (e.m <= rules.ext2) ? e.alpha : 0.0f;
+        a = (a >= rules.alpha_min) ? a : 0.0f;
+        a *= live;
+        const float Tn = T * (1.0f - a);
+        const bool stop = Tn < rules.T_min;
+        const float ab = stop ? 0.0f : a;   // alpha of a blended entry, else 0
+        const float wgt = T * ab;
+        C0 = fmaf(wgt, col.x, C0);
+        C1 = fmaf(wgt, col.y, C1);
+        C2 = fmaf(wgt, col.z, C2);
+        T = stop ? T : Tn;
+        last = (ab > 0.0f) ? (int32_t)__float_as_uint(col.w) : last;
+        live = stop ? 0.0f : live;
+      }
+      all_done = __ballot(live > 0.0f) == 0ull;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -298,16 +401,9 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   }
 }
 
-__device__ __forceinline__ int wave_max_int(int x) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) x = max(x, __shfl_xor(x, d, kWave));
-  return x;
-}
-
 // Value of lane l ^ XM (XM < 16: a partner in the same 16-lane row) through ds_swizzle
 // (bit mode, and-mask 0x1F): the exchange runs in the LDS crossbar, beside the VALU
-// work of the other waves, where a DPP operand would occupy the VALU (measured ~3%
-// faster on the backward blend than row_mirror / row_half_mirror / quad_perm DPP).
+// work of the other waves, where a DPP operand would occupy the VALU.
 template <int XM>
 __device__ __forceinline__ float lane_xor(float x) {
   static_assert(XM > 0 && XM < 16, "partner must be in the same row");
@@ -315,20 +411,35 @@ __device__ __forceinline__ float lane_xor(float x) {
                             __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), (XM << 10) | 0x1F));
 }
 
-// Wave sum of nine per-lane values as a reduce-scatter butterfly inside each 16-lane
+template <int XM>
+__device__ __forceinline__ int lane_xor_int(int x) {
+  static_assert(XM > 0 && XM < 16, "partner must be in the same row");
+  return __builtin_amdgcn_ds_swizzle(x, (XM << 10) | 0x1F);
+}
+
+// Largest value over the 16 lanes of each row.
+__device__ __forceinline__ int row_max_int(int x) {
+  x = max(x, lane_xor_int<1>(x));
+  x = max(x, lane_xor_int<2>(x));
+  x = max(x, lane_xor_int<4>(x));
+  x = max(x, lane_xor_int<8>(x));
+  return x;
+}
+
+// Row sum of nine per-lane values as a reduce-scatter butterfly inside each 16-lane
 // row: at every step a lane keeps half of its remaining values and adds its partner's
 // copy of them (9 -> 5 -> 3 -> 2 -> 1 registers). The partners l ^ 15 and l ^ 7 differ
 // in all low bits, so they come first (split on bit 3, then bit 2), then l ^ 2 and
-// l ^ 1. Two cross-row exchanges finish the sum. In-row lane l then holds the total of
-// value reduce_index(l) when bit l of kReduceLanes is set.
+// l ^ 1. Row lane l then holds its row's total of value reduce_index(l) when bit l of
+// kReduceLanes is set.
 constexpr uint32_t kReduceLanes = 0x1737u;  // row lanes 0, 1, 2, 4, 5, 8, 9, 10, 12
 __device__ __forceinline__ int reduce_index(uint32_t l) {
   return 5 * ((l >> 3) & 1) + 3 * ((l >> 2) & 1) + 2 * ((l >> 1) & 1) + (l & 1);
 }
 
-__device__ __forceinline__ float wave_reduce9_scatter(float a0, float a1, float a2, float a3,
-                                                      float a4, float a5, float a6, float a7,
-                                                      float a8) {
+__device__ __forceinline__ float row_reduce9_scatter(float a0, float a1, float a2, float a3,
+                                                     float a4, float a5, float a6, float a7,
+                                                     float a8) {
   const uint32_t l = __lane_id() & 15;
   const bool h3 = l & 8, h2 = l & 4, h1 = l & 2, h0 = l & 1;
   const float x0 = (h3 ? a5 : a0) + lane_xor<15>(h3 ? a0 : a5);
@@ -341,10 +452,7 @@ __device__ __forceinline__ float wave_reduce9_scatter(float a0, float a1, float 
   const float y2 = (h2 ? 0.0f : x2) + lane_xor<7>(h2 ? x2 : 0.0f);
   const float z0 = (h1 ? y2 : y0) + lane_xor<2>(h1 ? y0 : y2);
   const float z1 = (h1 ? 0.0f : y1) + lane_xor<2>(h1 ? y1 : 0.0f);
-  float v = (h0 ? z1 : z0) + lane_xor<1>(h0 ? z0 : z1);
-  v += __shfl_xor(v, 16, kWave);
-  v += __shfl_xor(v, 32, kWave);
-  return v;
+  return (h0 ? z1 : z0) + lane_xor<1>(h0 ? z0 : z1);
 }
 
 template <int TS, int R, bool LIMIT>
@@ -356,13 +464,14 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
                   float* __restrict__ grad2d) {
   constexpr int WPT = (TS / 8) * (TS / 8);
   constexpr int BATCH = R * kWave;
-  __shared__ float4 s_geo[WPT][BATCH];
-  __shared__ float4 s_shape[WPT][BATCH];
-  __shared__ float4 s_col[WPT][BATCH];
-  __shared__ uint32_t s_pos[WPT][BATCH];
+  __shared__ WaveLds<BATCH> s_lds[WPT];
+  __shared__ float s_acc[WPT][GS_GRAD2D_FLOATS][BATCH];   // per staged entry, the wave's sums
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  WaveLds<BATCH>& s = s_lds[threadIdx.x / kWave];
+  float (*acc)[BATCH] = s_acc[threadIdx.x / kWave];
+  const int lane = threadIdx.x % kWave;
+  init_null_entry(s);
   uint32_t start, end;
   tile_range(ranges, w.tile, tv.n_inst, start, end);
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
@@ -382,12 +491,16 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   // only g . B is ever needed, where B is the colour accumulated behind the current
   // Gaussian (initially T_final bg): dC/dalpha_i . g = T_i (g . c_i) - (g . B_i) / (1 - alpha_i)
   float S = T * (g0 * rules.bg[0] + g1 * rules.bg[1] + g2 * rules.bg[2]);
-  // the walk starts at the wave's last contributor, bounded by the tile's list so that
+  // each row's walk starts at its last contributor, bounded by the tile's list so that
   // a last_idx not written by the forward pass cannot send the gathers out of range
-  const int64_t wave_last = std::min<int64_t>(wave_max_int(last), (int64_t)end - 1);
-  if (wave_last < (int64_t)start) return;  // no pixel of this wave blended anything
-  const bool atomic_lane = lane < 16 && ((kReduceLanes >> lane) & 1u);
-  const int atomic_slot = reduce_index((uint32_t)lane);
+  const int rl = min(row_max_int(last), (int32_t)end - 1);
+  int32_t row_lim[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) row_lim[r] = __builtin_amdgcn_readlane(rl, r * kRowLanes);
+  const int32_t wave_last = max(max(row_lim[0], row_lim[1]), max(row_lim[2], row_lim[3]));
+  if (wave_last < (int32_t)start) return;  // no pixel of this wave blended anything
+  const bool atomic_lane = (kReduceLanes >> (lane % kRowLanes)) & 1u;
+  const int atomic_slot = reduce_index((uint32_t)(lane % kRowLanes));
   // limited-gradient ablation: count the pixel's blended Gaussians first, so the
   // back-to-front walk knows each one's front-to-back rank
   int n_blended = 0, from_back = 0;
@@ -396,31 +509,40 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       const int64_t bot = max((int64_t)start, top - (BATCH - 1));
       Ahead<R> cur;
       load_ahead<R>(vals, bot, top, cur);
-      const int cnt = stage_batch<R>(record, cur, bot, w, rules, s_geo[wave], s_shape[wave],
-                                     s_col[wave], s_pos[wave]);
-      for (int k = cnt - 1; k >= 0; --k) {
-        const int32_t pos = (int32_t)s_pos[wave][k];
+      int n_kept;
+      const int n_steps = stage_round<R, false>(record, cur, bot, w, rules, row_lim, s, n_kept);
+      for (int k = 0; k < n_steps; ++k) {
+        const int slot = row_slot(s, w.row, k);
+        const int32_t pos = (int32_t)__float_as_uint(s.aux[slot].z);
         Eval e;
-        eval_alpha(s_geo[wave][k], s_shape[wave][k], fpx, fpy, rules, e);
+        eval_alpha(s.geo[slot], s.shape[slot], fpx, fpy, rules, e);
         n_blended += ((pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min)) ? 1 : 0;
       }
       __builtin_amdgcn_wave_barrier();
     }
   }
   Ahead<R> ahead;
-  load_ahead<R>(vals, max((int64_t)start, wave_last - (BATCH - 1)), wave_last, ahead);
+  load_ahead<R>(vals, max((int64_t)start, (int64_t)wave_last - (BATCH - 1)), wave_last, ahead);
   for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
     const int64_t bot = max((int64_t)start, top - (BATCH - 1));
     const Ahead<R> cur = ahead;
-    const int cnt = stage_batch<R>(record, cur, bot, w, rules, s_geo[wave], s_shape[wave],
-                                   s_col[wave], s_pos[wave]);
-    const int64_t ntop = top - BATCH;   // the next batch, [max(start, ntop - BATCH + 1), ntop]
+    // this round's per-entry gradient sums start at zero
+#pragma unroll
+    for (int c = 0; c < GS_GRAD2D_FLOATS; ++c)
+      for (int j = lane; j < BATCH; j += kWave) acc[c][j] = 0.0f;
+    int n_kept;
+    const int n_steps = stage_round<R, false>(record, cur, bot, w, rules, row_lim, s, n_kept);
+    const int64_t ntop = top - BATCH;   // the next round, [max(start, ntop - BATCH + 1), ntop]
     load_ahead<R>(vals, max((int64_t)start, ntop - (BATCH - 1)), ntop, ahead);
-    for (int k = cnt - 1; k >= 0; --k) {
-      const float4 geo = s_geo[wave][k];
-      const float4 shape = s_shape[wave][k];
-      const float4 col = s_col[wave][k];
-      const int32_t pos = (int32_t)s_pos[wave][k];
+    uint32_t word = 0;
+    for (int k = 0; k < n_steps; ++k) {
+      if ((k & 3) == 0) word = s.idx[w.row * (BATCH / 4) + (k >> 2)];   // four steps' slots
+      const int slot = (word >> (8 * (k & 3))) & 0xFF;
+      const float4 geo = s.geo[slot];
+      const float4 shape = s.shape[slot];
+      const float4 col = s.col[slot];
+      const float4 aux = s.aux[slot];
+      const int32_t pos = (int32_t)__float_as_uint(aux.z);
       Eval e;
       eval_alpha(geo, shape, fpx, fpy, rules, e);
       // branch-free: non-contributing lanes add zeros and keep their state
@@ -441,17 +563,32 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       // alpha = min(alpha_max, o G): no gradient through a clamped alpha
       dalpha = (grad_on && shape.w * e.G <= rules.alpha_max) ? dalpha : 0.0f;
       const float d_o = dalpha * e.G;
-      // dalpha/dm = -alpha / 2; m = e0^2 + e1^2, e0 = w00 dx, e1 = w10 dx + w11 dy, dx = pixel - mean
+      // dalpha/dm = -alpha / 2; m = e0^2 + e1^2 with e = L^-1 d, d = pixel - mean
       const float q = -dalpha * e.alpha;
       const float t0 = q * e.e0, t1 = q * e.e1;
       const float d_mx = -fmaf(t0, shape.x, t1 * shape.y);
       const float d_my = -(t1 * shape.z);
-      const float d_w00 = t0 * e.dx, d_w10 = t1 * e.dx, d_w11 = t1 * e.dy;
-      if (__ballot(grad_on) != 0ull) {
-        const float tot = wave_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g,
-                                               d_b);
-        if (atomic_lane)
-          atomicAdd(grad2d + (size_t)__float_as_uint(col.w) * GS_GRAD2D_FLOATS + atomic_slot, tot);
+      const float dx = e.di - aux.x, dy = e.dj - aux.y;
+      const float d_w00 = t0 * dx, d_w10 = t1 * dx, d_w11 = t1 * dy;
+      const uint64_t gm = __ballot(grad_on);
+      if (gm != 0ull) {
+        const float tot = row_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g, d_b);
+        // a row adds its Gaussian's totals only if one of its pixels passed gradient
+        const bool row_has = ((gm >> (kRowLanes * w.row)) & 0xFFFFull) != 0ull;
+        if (atomic_lane && row_has && slot < BATCH) atomicAdd(&acc[atomic_slot][slot], tot);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // one global addition per staged entry and gradient component: the rows' sums of
+    // an entry are combined in LDS first, and nine consecutive lanes cover the nine
+    // components of one entry (one record), seven entries per instruction
+    for (int b = 0; b < n_kept; b += 7) {
+      const int e_slot = b + lane / GS_GRAD2D_FLOATS, c = lane % GS_GRAD2D_FLOATS;
+      if (lane < 7 * GS_GRAD2D_FLOATS && e_slot < n_kept) {
+        const float v = acc[c][e_slot];
+        const uint32_t rec = __float_as_uint(s.col[e_slot].w);
+        if (v != 0.0f && rec < tv.n_records) atomicAdd(grad2d + (size_t)rec * GS_GRAD2D_FLOATS + c, v);
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -579,10 +716,12 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
     return launch_status();
   }
 #undef GS_BWD_LIMITED
+  // 32x32 tiles stage 64 entries per wave and round whatever lds_batch says: sixteen
+  // waves with 128-entry rounds would not fit the workgroup's LDS
   const bool two = cfg->lds_batch == 128;
   switch (cfg->tile_size) {
     case 8: if (two) GS_BWD(8, 2); else GS_BWD(8, 1); break;
-    case 32: if (two) GS_BWD(32, 2); else GS_BWD(32, 1); break;
+    case 32: GS_BWD(32, 1); break;
     default: if (two) GS_BWD(16, 2); else GS_BWD(16, 1); break;
   }
 #undef GS_BWD
