@@ -92,8 +92,8 @@ typedef struct gs_config {
   float T_min;             /* stop before transmittance falls below this, 1e-4 */
   float bg[3];             /* background colour added as T_final * bg */
   int32_t sort_digit_bits; /* radix digit width of gs_sort: 4..8, default 8 */
-  int32_t lds_batch;       /* list entries each wave stages in LDS per round: 64 or 128
-                              (0 = 64); changes speed only */
+  int32_t lds_batch;       /* list entries each wave stages in LDS per round: 32, 64 or
+                              128 (0 = 64); changes speed only */
   /* Ablation switches of Sec. 7.3 (0 in the method itself): */
   int32_t isotropic;       /* 1: one radius on all axes, Sigma = s^2 I with s = exp of the
                               mean of the three log-scales; quaternions unused, zero

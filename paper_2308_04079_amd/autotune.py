@@ -1,8 +1,8 @@
 """Autotuner for the knobs that change speed but not results.
 
 Tile size (8, 16, 32; the image is tile-size independent because a Gaussian reaches a
-pixel only inside its 3-sigma ellipse), the LDS batch depth of the blend kernels (64 or
-128 list entries staged per wave and round) and the radix digit width of the sort (6, 7,
+pixel only inside its 3-sigma ellipse), the LDS batch depth of the blend kernels (32, 64
+or 128 list entries staged per wave and round) and the radix digit width of the sort (6, 7,
 8 bits; the sort is stable either way) are timed on the caller's own scene and views,
 one full step (forward, L1 gradient, backward) per trial, and the fastest combination
 is kept in a JSON cache keyed by device, Gaussian count (power-of-two bucket), SH
@@ -19,7 +19,7 @@ import torch
 from .raster import Rasterizer, l1_loss_grad
 
 TILE_SIZES = (8, 16, 32)
-LDS_BATCHES = (64, 128)
+LDS_BATCHES = (32, 64, 128)
 DIGIT_BITS = (6, 7, 8)
 
 

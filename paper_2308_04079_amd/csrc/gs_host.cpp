@@ -16,7 +16,8 @@ int check_config(const gs_config* cfg) {
     return GS_ERR_ARG;
   if (!(cfg->T_min > 0.0f) || !(cfg->T_min < 1.0f)) return GS_ERR_ARG;
   if (cfg->sort_digit_bits < 4 || cfg->sort_digit_bits > 8) return GS_ERR_ARG;
-  if (cfg->lds_batch != 0 && cfg->lds_batch != 64 && cfg->lds_batch != 128) return GS_ERR_ARG;
+  if (cfg->lds_batch != 0 && cfg->lds_batch != 32 && cfg->lds_batch != 64 && cfg->lds_batch != 128)
+    return GS_ERR_ARG;
   if (cfg->isotropic != 0 && cfg->isotropic != 1) return GS_ERR_ARG;
   if (cfg->grad_limit < 0) return GS_ERR_ARG;
   for (int c = 0; c < 3; ++c)

@@ -2,20 +2,20 @@
 // BlendInOrder; Eq. front-to-back; App. C) and its back-to-front adjoint (Sec. 6).
 //
 // One workgroup per (view, tile); each 64-lane wave owns an 8x8 pixel block of the
-// tile, and each 16-lane row of the wave a 4x4 block of that. A wave walks the tile's
-// instance list in rounds of 64 entries (one gathered per lane); each entry is tested
-// against the four 4x4 blocks of its rows and kept for a row only if some pixel of
-// that block can take it. Kept entries are compacted into the wave's LDS slice and
-// each row gets the list of its own entries; the rows then blend their lists side by
-// side, one entry per row per step (four Gaussians per wave instruction). Small
-// blocks follow the small footprints of typical Gaussians much more tightly than the
-// 8x8 block of a whole wave. Waves never wait for each other, so no workgroup
-// barrier is needed; a wave stops as soon as all 64 of its pixels are saturated.
+// tile and walks the tile's instance list in rounds of BATCH entries (one gathered per
+// lane), keeping in its LDS slice only the entries that can reach a pixel of its block.
+// Waves never wait for each other, so no workgroup barrier is needed.
 //
-// The backward pass walks the same lists back to front from each row's last
-// contributor, recovers T by dividing the stored final T by (1 - alpha), and sums
-// the nine per-pixel partial gradients of each row's Gaussian over the row's 16
-// lanes with lane exchanges before nine lanes per row issue the global atomics.
+// Forward: each 16-lane row of a wave owns a 4x4 block of the wave's block; every
+// entry is tested against the four 4x4 blocks and each row gets the list of its own
+// entries. The rows then blend their lists side by side, one entry per row per step
+// (four Gaussians per wave instruction), and a wave stops as soon as all 64 of its
+// pixels are saturated.
+//
+// Backward: the wave walks its kept entries back to front from the block's last
+// contributor, one Gaussian per step over all 64 pixels, recovers T by dividing the
+// stored final T by (1 - alpha), sums the nine per-pixel gradient terms over the wave
+// with lane exchanges, and nine lanes issue the Gaussian's global atomics.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -24,8 +24,8 @@ namespace gs {
 
 // Per-Gaussian LDS entry: geo = (centre of the box's corner pixel, whitened offset c of
 // that centre from the mean), shape = (w00, w10, w11, opacity), col = (r, g, b, list
-// position or record index), aux = (offset a of the mean from the corner centre, list
-// position; the backward only).
+// position (forward) or record index (backward)), and for the backward the list
+// position in pos.
 struct Eval {
   float di, dj, e0, e1, m, G, alpha;
 };
@@ -209,33 +209,29 @@ struct WaveLds {
   float4 geo[BATCH + 1];
   float4 shape[BATCH + 1];
   float4 col[BATCH + 1];
-  float4 aux[BATCH + 1];             // written and read by the backward only
   uint32_t idx[kRows * BATCH / 4];   // row r's k-th slot: byte k of idx[r * BATCH / 4 ...]
 };
 
-// The null entry: zero shape and opacity give alpha = 0 < alpha_min at every pixel, and
-// its list position is past every last contributor.
+// The null entry: zero shape and opacity give alpha = 0 < alpha_min at every pixel.
 template <int BATCH>
 __device__ __forceinline__ void init_null_entry(WaveLds<BATCH>& s) {
   if (__lane_id() == 0) {
     s.geo[BATCH] = make_float4(0, 0, 0, 0);
     s.shape[BATCH] = make_float4(0, 0, 0, 0);
     s.col[BATCH] = make_float4(0, 0, 0, __uint_as_float(0xFFFFFFFFu));
-    s.aux[BATCH] = make_float4(0, 0, __uint_as_float(0x7FFFFFFFu), 0);
   }
 }
 
 // Compact the kept entries of the wave into its LDS slice (slots in lane order) and
-// write every row's slot list: front to back (FWD) or back to front. Slots of a row
-// past its count point at the null entry. Returns the largest row count.
-template <int BATCH, int R, bool FWD>
+// write every row's slot list front to back. Slots of a row past its count point at
+// the null entry. Returns the largest row count.
+template <int BATCH, int R>
 __device__ __forceinline__ int commit_round(const Entry* e, WaveLds<BATCH>& s, int& n_kept) {
   constexpr uint32_t kNull = (uint32_t)BATCH * 0x01010101u;
   const int lane = threadIdx.x % kWave;
   for (int w = lane; w < kRows * BATCH / 4; w += kWave) s.idx[w] = kNull;
   const uint64_t lt = lanemask_lt();
-  // all ballots first: each row's count of the round is then known, so the backward
-  // can write its list back to front directly
+  // all ballots first, then the writes
   uint64_t km[R], br[R][kRows];
   int cnt[kRows] = {0, 0, 0, 0};
 #pragma unroll
@@ -257,16 +253,13 @@ __device__ __forceinline__ int commit_round(const Entry* e, WaveLds<BATCH>& s, i
     if (x.rows) {
       s.geo[slot] = make_float4((float)x.ilo + 0.5f, (float)x.jlo + 0.5f, x.r0.z, x.r0.w);
       s.shape[slot] = x.r1;
-      // the forward keeps the list position in col.w; the backward keeps the record
-      // index there (it arrives with the colour, for the atomics), the position in aux
-      s.col[slot] = make_float4(x.r2.x, x.r2.y, x.r2.z, __uint_as_float(FWD ? x.i : x.g));
-      if (!FWD) s.aux[slot] = make_float4(x.ax, x.ay, __uint_as_float(x.i), 0.0f);
+      s.col[slot] = make_float4(x.r2.x, x.r2.y, x.r2.z, __uint_as_float(x.i));
     }
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       if ((x.rows >> r) & 1u) {
         const int q = before[r] + __popcll(br[sub][r] & lt);   // rank in list order
-        idx8[r * BATCH + (FWD ? q : cnt[r] - 1 - q)] = (uint8_t)slot;
+        idx8[r * BATCH + q] = (uint8_t)slot;
       }
       before[r] += __popcll(br[sub][r]);
     }
@@ -287,47 +280,48 @@ struct Ahead {
   uint32_t g[R];
 };
 
-template <int R>
+template <int BATCH>
+constexpr int lanes_rounds() { return (BATCH + kWave - 1) / kWave; }
+
+// Values of the BATCH entries [first, first + BATCH), entry r * 64 + lane in a.g[r]
+// (a round of 32 entries leaves lanes 32..63 empty).
+template <int BATCH>
 __device__ __forceinline__ void load_ahead(const uint32_t* __restrict__ vals, int64_t first,
-                                           int64_t last_ok, Ahead<R>& a) {
+                                           int64_t last_ok, Ahead<lanes_rounds<BATCH>()>& a) {
   const int lane = threadIdx.x % kWave;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
+  for (int r = 0; r < lanes_rounds<BATCH>(); ++r) {
     const int64_t i = first + r * kWave + lane;
-    a.g[r] = (i <= last_ok) ? vals[i] : ~0u;
+    a.g[r] = (r * kWave + lane < BATCH && i <= last_ok) ? vals[i] : ~0u;
   }
 }
 
-// Stage the R * 64 consecutive list entries [first, first + 64 R) whose values `a`
+// Stage the BATCH consecutive list entries [first, first + BATCH) whose values `a`
 // holds (all gathers are issued before any ballot). Returns the largest row count;
 // n_kept receives the number of staged entries.
-template <int R, bool FWD>
-__device__ __forceinline__ int stage_round(const float* __restrict__ record, const Ahead<R>& a,
-                                           int64_t first, const WaveTile& w, const Rules& rules,
-                                           const int32_t* row_lim, WaveLds<R * kWave>& s,
+template <int BATCH>
+__device__ __forceinline__ int stage_round(const float* __restrict__ record,
+                                           const Ahead<lanes_rounds<BATCH>()>& a, int64_t first,
+                                           const WaveTile& w, const Rules& rules,
+                                           const int32_t* row_lim, WaveLds<BATCH>& s,
                                            int& n_kept) {
+  constexpr int R = lanes_rounds<BATCH>();
   Entry e[R];
   const int lane = threadIdx.x % kWave;
 #pragma unroll
   for (int r = 0; r < R; ++r)
     gather_entry(record, a.g[r], (uint32_t)(first + r * kWave + lane), w, rules, row_lim, e[r]);
-  return commit_round<R * kWave, R, FWD>(e, s, n_kept);
+  return commit_round<BATCH, R>(e, s, n_kept);
 }
 
-// Slot of this lane's row at step k (four steps per LDS word).
-template <int BATCH>
-__device__ __forceinline__ int row_slot(const WaveLds<BATCH>& s, int row, int k) {
-  return (s.idx[row * (BATCH / 4) + (k >> 2)] >> (8 * (k & 3))) & 0xFF;
-}
-
-template <int TS, int R>
+template <int TS, int BATCH>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
                   TileViews tv, Rules rules, float* __restrict__ image,
                   float* __restrict__ T_final, int32_t* __restrict__ last_idx) {
   constexpr int WPT = (TS / 8) * (TS / 8);
-  constexpr int BATCH = R * kWave;
+  constexpr int R = lanes_rounds<BATCH>();
   __shared__ WaveLds<BATCH> s_lds[WPT];
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
@@ -343,7 +337,7 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   // combining of lane masks
   float live = w.inside ? 1.0f : 0.0f;
   Ahead<R> ahead;
-  load_ahead<R>(vals, start, (int64_t)end - 1, ahead);
+  load_ahead<BATCH>(vals, start, (int64_t)end - 1, ahead);
   for (uint32_t base = start; base < end; base += BATCH) {
     const uint64_t lv = __ballot(live > 0.0f);
     if (lv == 0ull) break;
@@ -352,8 +346,8 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
     for (int r = 0; r < kRows; ++r) row_lim[r] = ((lv >> (kRowLanes * r)) & 0xFFFFull) ? INT32_MAX : -1;
     const Ahead<R> cur = ahead;
     int n_kept;
-    const int n_steps = stage_round<R, true>(record, cur, base, w, rules, row_lim, s, n_kept);
-    load_ahead<R>(vals, (int64_t)base + BATCH, (int64_t)end - 1, ahead);
+    const int n_steps = stage_round<BATCH>(record, cur, base, w, rules, row_lim, s, n_kept);
+    load_ahead<BATCH>(vals, (int64_t)base + BATCH, (int64_t)end - 1, ahead);
     // groups of 8 steps; the saturation ballot runs once per group
     bool all_done = false;
     for (int k0 = 0; k0 < n_steps && !all_done; k0 += 8) {
@@ -403,7 +397,8 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
 
 // Value of lane l ^ XM (XM < 16: a partner in the same 16-lane row) through ds_swizzle
 // (bit mode, and-mask 0x1F): the exchange runs in the LDS crossbar, beside the VALU
-// work of the other waves, where a DPP operand would occupy the VALU.
+// work of the other waves, where a DPP operand would take a VALU issue slot (the
+// backward blend is bound by its VALU issue; measured a few percent faster).
 template <int XM>
 __device__ __forceinline__ float lane_xor(float x) {
   static_assert(XM > 0 && XM < 16, "partner must be in the same row");
@@ -455,7 +450,101 @@ __device__ __forceinline__ float row_reduce9_scatter(float a0, float a1, float a
   return (h0 ? z1 : z0) + lane_xor<1>(h0 ? z0 : z1);
 }
 
-template <int TS, int R, bool LIMIT>
+// ---------------------------------------------------------------------------
+// backward: one Gaussian per step over the wave's whole 8x8 block
+// ---------------------------------------------------------------------------
+
+// LDS slice of one wave for the backward: the kept entries of a round in list order
+// (geo, shape, colour with the record index, and aux = (offset a of the mean from the
+// corner pixel centre, list position)).
+template <int BATCH>
+struct BwdLds {
+  float4 geo[BATCH];
+  float4 shape[BATCH];
+  float4 col[BATCH];
+  float4 aux[BATCH];
+};
+
+// List entry i (record g) for the backward: kept if some pixel of the wave's 8x8 block
+// can take it (the block test of gather_entry over the whole block).
+__device__ __forceinline__ bool gather_block_entry(const float* __restrict__ record, uint32_t g,
+                                                   const WaveTile& w, const Rules& rules,
+                                                   float4& r0, float4& r1, float4& r2,
+                                                   float& ax, float& ay) {
+  r0 = r1 = r2 = make_float4(0, 0, 0, 0);
+  ax = ay = 0.0f;
+  if (g >= w.n_records) return false;
+  const float4* rec = reinterpret_cast<const float4*>(record + (size_t)g * GS_RECORD_FLOATS);
+  r0 = rec[0];
+  const int lo = __float_as_int(r0.x), hi = __float_as_int(r0.y);
+  const int ilo = lo & 0xFFFF, jlo = (lo >> 16) & 0xFFFF;
+  const int ihi = hi & 0xFFFF, jhi = (hi >> 16) & 0xFFFF;
+  const int bx1 = min(w.x0 + 7, w.W - 1), by1 = min(w.y0 + 7, w.H - 1);
+  if (ilo > bx1 || ihi < w.x0 || jlo > by1 || jhi < w.y0) return false;
+  r1 = rec[1];
+  Shape sh;
+  sh.w00 = r1.x;
+  sh.w10 = r1.y;
+  sh.w11 = r1.z;
+  sh.c0 = r0.z;
+  sh.c1 = r0.w;
+  sh.i11 = __builtin_amdgcn_rcpf(sh.w11);
+  sh.iq = __builtin_amdgcn_rcpf(fmaf(sh.w00, sh.w00, sh.w10 * sh.w10));
+  // the mean's offset from the corner centre: L^-1 a = -c
+  ax = -sh.c0 * __builtin_amdgcn_rcpf(sh.w00);
+  ay = -fmaf(sh.w10, ax, sh.c1) * sh.i11;
+  const float thr = fminf(rules.ext2, 2.0f * (__logf(r1.w) - rules.log_alpha_min));
+  if (!block_reachable(sh, thr, ax, ay, (float)(w.x0 - ilo), (float)(bx1 - ilo),
+                       (float)(w.y0 - jlo), (float)(by1 - jlo)))
+    return false;
+  r2 = rec[2];
+  return true;
+}
+
+// Stage the entries [first, first + BATCH) whose values `a` holds: the kept ones in
+// list order from slot 0. Returns the kept count.
+template <int BATCH>
+__device__ __forceinline__ int stage_block_round(const float* __restrict__ record,
+                                                 const Ahead<lanes_rounds<BATCH>()>& a,
+                                                 int64_t first, const WaveTile& w,
+                                                 const Rules& rules, BwdLds<BATCH>& s) {
+  constexpr int R = lanes_rounds<BATCH>();
+  const int lane = threadIdx.x % kWave;
+  float4 r0[R], r1[R], r2[R];
+  float ax[R], ay[R];
+  bool keep[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    keep[r] = gather_block_entry(record, a.g[r], w, rules, r0[r], r1[r], r2[r], ax[r], ay[r]);
+  const uint64_t lt = lanemask_lt();
+  int cnt = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t km = __ballot(keep[r]);
+    if (keep[r]) {
+      const int slot = cnt + __popcll(km & lt);
+      const int lo = __float_as_int(r0[r].x);
+      s.geo[slot] = make_float4((float)(lo & 0xFFFF) + 0.5f, (float)((lo >> 16) & 0xFFFF) + 0.5f,
+                                r0[r].z, r0[r].w);
+      s.shape[slot] = r1[r];
+      s.col[slot] = make_float4(r2[r].x, r2[r].y, r2[r].z, __uint_as_float(a.g[r]));
+      s.aux[slot] = make_float4(ax[r], ay[r], __uint_as_float((uint32_t)(first + r * kWave + lane)), 0.0f);
+    }
+    cnt += __popcll(km);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return cnt;
+}
+
+// Largest value over the wave.
+__device__ __forceinline__ int wave_max_int(int x) {
+  x = row_max_int(x);
+  x = max(x, __shfl_xor(x, 16, kWave));
+  return max(x, __shfl_xor(x, 32, kWave));
+}
+
+template <int TS, int BATCH, bool LIMIT>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
@@ -463,24 +552,23 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
                   const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimage,
                   float* __restrict__ grad2d) {
   constexpr int WPT = (TS / 8) * (TS / 8);
-  constexpr int BATCH = R * kWave;
-  __shared__ WaveLds<BATCH> s_lds[WPT];
-  __shared__ float s_acc[WPT][GS_GRAD2D_FLOATS][BATCH];   // per staged entry, the wave's sums
+  __shared__ BwdLds<BATCH> s_lds[WPT];
   WaveTile w;
   if (!wave_tile<TS>(tv, tile_order, w)) return;
-  WaveLds<BATCH>& s = s_lds[threadIdx.x / kWave];
-  float (*acc)[BATCH] = s_acc[threadIdx.x / kWave];
+  BwdLds<BATCH>& s = s_lds[threadIdx.x / kWave];
   const int lane = threadIdx.x % kWave;
-  init_null_entry(s);
+  // the wave's 8x8 block: lane l owns pixel (l & 7, l >> 3) of it
+  const int px = w.x0 + (lane & 7), py = w.y0 + (lane >> 3);
+  const bool inside = px < w.W && py < w.H;
   uint32_t start, end;
   tile_range(ranges, w.tile, tv.n_inst, start, end);
-  const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
   int32_t last = -1;
-  if (w.inside) {
+  if (inside) {
     const int64_t P = tv.pix_offset[w.v];
     const int64_t HW = (int64_t)w.W * w.H;
-    const int64_t p = (int64_t)w.py * w.W + w.px;
+    const int64_t p = (int64_t)py * w.W + px;
     T = T_final[P + p];
     last = last_idx[P + p];
     const float* dimg = dL_dimage + 3 * P;
@@ -491,57 +579,43 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   // only g . B is ever needed, where B is the colour accumulated behind the current
   // Gaussian (initially T_final bg): dC/dalpha_i . g = T_i (g . c_i) - (g . B_i) / (1 - alpha_i)
   float S = T * (g0 * rules.bg[0] + g1 * rules.bg[1] + g2 * rules.bg[2]);
-  // each row's walk starts at its last contributor, bounded by the tile's list so that
+  // the walk starts at the wave's last contributor, bounded by the tile's list so that
   // a last_idx not written by the forward pass cannot send the gathers out of range
-  const int rl = min(row_max_int(last), (int32_t)end - 1);
-  int32_t row_lim[kRows];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) row_lim[r] = __builtin_amdgcn_readlane(rl, r * kRowLanes);
-  const int32_t wave_last = max(max(row_lim[0], row_lim[1]), max(row_lim[2], row_lim[3]));
+  const int32_t wave_last = min(wave_max_int(last), (int32_t)end - 1);
   if (wave_last < (int32_t)start) return;  // no pixel of this wave blended anything
-  const bool atomic_lane = (kReduceLanes >> (lane % kRowLanes)) & 1u;
-  const int atomic_slot = reduce_index((uint32_t)(lane % kRowLanes));
+  const bool atomic_lane = lane < kRowLanes && ((kReduceLanes >> lane) & 1u);
+  const int atomic_slot = reduce_index((uint32_t)lane);
   // limited-gradient ablation: count the pixel's blended Gaussians first, so the
   // back-to-front walk knows each one's front-to-back rank
   int n_blended = 0, from_back = 0;
   if constexpr (LIMIT) {
     for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
       const int64_t bot = max((int64_t)start, top - (BATCH - 1));
-      Ahead<R> cur;
-      load_ahead<R>(vals, bot, top, cur);
-      int n_kept;
-      const int n_steps = stage_round<R, false>(record, cur, bot, w, rules, row_lim, s, n_kept);
-      for (int k = 0; k < n_steps; ++k) {
-        const int slot = row_slot(s, w.row, k);
-        const int32_t pos = (int32_t)__float_as_uint(s.aux[slot].z);
+      Ahead<lanes_rounds<BATCH>()> cur;
+      load_ahead<BATCH>(vals, bot, top, cur);
+      const int cnt = stage_block_round<BATCH>(record, cur, bot, w, rules, s);
+      for (int k = 0; k < cnt; ++k) {
+        const int32_t pos = (int32_t)__float_as_uint(s.aux[k].z);
         Eval e;
-        eval_alpha(s.geo[slot], s.shape[slot], fpx, fpy, rules, e);
+        eval_alpha(s.geo[k], s.shape[k], fpx, fpy, rules, e);
         n_blended += ((pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min)) ? 1 : 0;
       }
       __builtin_amdgcn_wave_barrier();
     }
   }
-  Ahead<R> ahead;
-  load_ahead<R>(vals, max((int64_t)start, (int64_t)wave_last - (BATCH - 1)), wave_last, ahead);
+  Ahead<lanes_rounds<BATCH>()> ahead;
+  load_ahead<BATCH>(vals, max((int64_t)start, (int64_t)wave_last - (BATCH - 1)), wave_last, ahead);
   for (int64_t top = wave_last; top >= (int64_t)start; top -= BATCH) {
     const int64_t bot = max((int64_t)start, top - (BATCH - 1));
-    const Ahead<R> cur = ahead;
-    // this round's per-entry gradient sums start at zero
-#pragma unroll
-    for (int c = 0; c < GS_GRAD2D_FLOATS; ++c)
-      for (int j = lane; j < BATCH; j += kWave) acc[c][j] = 0.0f;
-    int n_kept;
-    const int n_steps = stage_round<R, false>(record, cur, bot, w, rules, row_lim, s, n_kept);
+    const Ahead<lanes_rounds<BATCH>()> cur = ahead;
+    const int cnt = stage_block_round<BATCH>(record, cur, bot, w, rules, s);
     const int64_t ntop = top - BATCH;   // the next round, [max(start, ntop - BATCH + 1), ntop]
-    load_ahead<R>(vals, max((int64_t)start, ntop - (BATCH - 1)), ntop, ahead);
-    uint32_t word = 0;
-    for (int k = 0; k < n_steps; ++k) {
-      if ((k & 3) == 0) word = s.idx[w.row * (BATCH / 4) + (k >> 2)];   // four steps' slots
-      const int slot = (word >> (8 * (k & 3))) & 0xFF;
-      const float4 geo = s.geo[slot];
-      const float4 shape = s.shape[slot];
-      const float4 col = s.col[slot];
-      const float4 aux = s.aux[slot];
+    load_ahead<BATCH>(vals, max((int64_t)start, ntop - (BATCH - 1)), ntop, ahead);
+    for (int k = cnt - 1; k >= 0; --k) {
+      const float4 geo = s.geo[k];
+      const float4 shape = s.shape[k];
+      const float4 col = s.col[k];
+      const float4 aux = s.aux[k];
       const int32_t pos = (int32_t)__float_as_uint(aux.z);
       Eval e;
       eval_alpha(geo, shape, fpx, fpy, rules, e);
@@ -564,31 +638,20 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       dalpha = (grad_on && shape.w * e.G <= rules.alpha_max) ? dalpha : 0.0f;
       const float d_o = dalpha * e.G;
       // dalpha/dm = -alpha / 2; m = e0^2 + e1^2 with e = L^-1 d, d = pixel - mean
+      // (d = D - a: the pixel's offset D from the corner centre, exact, minus the mean's)
       const float q = -dalpha * e.alpha;
       const float t0 = q * e.e0, t1 = q * e.e1;
       const float d_mx = -fmaf(t0, shape.x, t1 * shape.y);
       const float d_my = -(t1 * shape.z);
       const float dx = e.di - aux.x, dy = e.dj - aux.y;
       const float d_w00 = t0 * dx, d_w10 = t1 * dx, d_w11 = t1 * dy;
-      const uint64_t gm = __ballot(grad_on);
-      if (gm != 0ull) {
-        const float tot = row_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g, d_b);
-        // a row adds its Gaussian's totals only if one of its pixels passed gradient
-        const bool row_has = ((gm >> (kRowLanes * w.row)) & 0xFFFFull) != 0ull;
-        if (atomic_lane && row_has && slot < BATCH) atomicAdd(&acc[atomic_slot][slot], tot);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // one global addition per staged entry and gradient component: the rows' sums of
-    // an entry are combined in LDS first, and nine consecutive lanes cover the nine
-    // components of one entry (one record), seven entries per instruction
-    for (int b = 0; b < n_kept; b += 7) {
-      const int e_slot = b + lane / GS_GRAD2D_FLOATS, c = lane % GS_GRAD2D_FLOATS;
-      if (lane < 7 * GS_GRAD2D_FLOATS && e_slot < n_kept) {
-        const float v = acc[c][e_slot];
-        const uint32_t rec = __float_as_uint(s.col[e_slot].w);
-        if (v != 0.0f && rec < tv.n_records) atomicAdd(grad2d + (size_t)rec * GS_GRAD2D_FLOATS + c, v);
+      if (__ballot(grad_on) != 0ull) {
+        float tot = row_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g, d_b);
+        tot += __shfl_xor(tot, 16, kWave);
+        tot += __shfl_xor(tot, 32, kWave);
+        const uint32_t rec = __float_as_uint(col.w);
+        if (atomic_lane && tot != 0.0f && rec < tv.n_records)
+          atomicAdd(grad2d + (size_t)rec * GS_GRAD2D_FLOATS + atomic_slot, tot);
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -656,15 +719,22 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_instances* inst,
   const Rules rules = make_rules(cfg);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
-#define GS_FWD(TS, R)                                                                          \
-  render_fwd_kernel<TS, R><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                      \
+  const int batch = cfg->lds_batch == 0 ? 64 : cfg->lds_batch;
+#define GS_FWD(TS, B)                                                                          \
+  render_fwd_kernel<TS, B><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                      \
       proj->record, inst->vals, tile_ranges, tile_order, tv, rules, image, T_final, last_idx)
-  const bool two = cfg->lds_batch == 128;
-  switch (cfg->tile_size) {
-    case 8: if (two) GS_FWD(8, 2); else GS_FWD(8, 1); break;
-    case 32: if (two) GS_FWD(32, 2); else GS_FWD(32, 1); break;
-    default: if (two) GS_FWD(16, 2); else GS_FWD(16, 1); break;
+#define GS_FWD_BATCH(TS)                                                                       \
+  switch (batch) {                                                                             \
+    case 32: GS_FWD(TS, 32); break;                                                            \
+    case 128: GS_FWD(TS, 128); break;                                                          \
+    default: GS_FWD(TS, 64); break;                                                            \
   }
+  switch (cfg->tile_size) {
+    case 8: GS_FWD_BATCH(8); break;
+    case 32: GS_FWD_BATCH(32); break;
+    default: GS_FWD_BATCH(16); break;
+  }
+#undef GS_FWD_BATCH
 #undef GS_FWD
   return launch_status();
 }
@@ -698,12 +768,12 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
   const Rules rules = make_rules(cfg);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)tv.tile_offset[n_views]);
-#define GS_BWD(TS, R)                                                                          \
-  render_bwd_kernel<TS, R, false><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(               \
+#define GS_BWD(TS, B)                                                                          \
+  render_bwd_kernel<TS, B, false><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(               \
       proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
       dL_dimage, grad2d)
 #define GS_BWD_LIMITED(TS)                                                                     \
-  render_bwd_kernel<TS, 1, true><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(                \
+  render_bwd_kernel<TS, 64, true><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(               \
       proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
       dL_dimage, grad2d)
   if (cfg->grad_limit > 0) {
@@ -716,13 +786,19 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
     return launch_status();
   }
 #undef GS_BWD_LIMITED
-  // 32x32 tiles stage 64 entries per wave and round whatever lds_batch says: sixteen
-  // waves with 128-entry rounds would not fit the workgroup's LDS
-  const bool two = cfg->lds_batch == 128;
+  // 32x32 tiles stage at most 64 entries per wave and round: sixteen waves with
+  // 128-entry rounds would not fit the workgroup's LDS
+  const int batch = cfg->lds_batch == 0 ? 64 : cfg->lds_batch;
   switch (cfg->tile_size) {
-    case 8: if (two) GS_BWD(8, 2); else GS_BWD(8, 1); break;
-    case 32: GS_BWD(32, 1); break;
-    default: if (two) GS_BWD(16, 2); else GS_BWD(16, 1); break;
+    case 8:
+      if (batch == 32) GS_BWD(8, 32); else if (batch == 128) GS_BWD(8, 128); else GS_BWD(8, 64);
+      break;
+    case 32:
+      if (batch == 32) GS_BWD(32, 32); else GS_BWD(32, 64);
+      break;
+    default:
+      if (batch == 32) GS_BWD(16, 32); else if (batch == 128) GS_BWD(16, 128); else GS_BWD(16, 64);
+      break;
   }
 #undef GS_BWD
   return launch_status();

@@ -133,7 +133,8 @@ def test_forward_image_matches_oracle(name):
     compare_images(state, sc, cams)
 
 
-@pytest.mark.parametrize("tile,batch", [(8, 64), (32, 64), (16, 128), (8, 128)])
+@pytest.mark.parametrize("tile,batch", [(8, 64), (32, 64), (16, 128), (8, 128), (16, 32),
+                                        (32, 32)])
 def test_tile_size_and_batch_depth_do_not_change_image(tile, batch):
     sc, cams = CASES["ragged"]
     _, _, s16 = gpu_render(sc, cams)
@@ -162,7 +163,8 @@ def backward_case(sc, cams, seed, tiles=None, **cfg):
                          [("offcentre", {"lds_batch": 128}), ("ragged", {"tile_size": 32}),
                           ("small", {"tile_size": 8}),
                           ("offcentre", {"tile_size": 8, "lds_batch": 128}),
-                          ("ragged", {"tile_size": 32, "lds_batch": 128})])
+                          ("ragged", {"tile_size": 32, "lds_batch": 128}),
+                          ("ragged", {"lds_batch": 32}), ("offcentre", {"tile_size": 8, "lds_batch": 32})])
 def test_backward_matches_oracle(name, cfg):
     sc, cams = CASES[name]
     grads, grad2d, gref, acc, p = backward_case(sc, cams, 5, **cfg)
