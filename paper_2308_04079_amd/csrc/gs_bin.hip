@@ -100,11 +100,12 @@ struct TileRect {
 };
 
 __device__ __forceinline__ TileRect tile_rect(int2 lohi, int T) {
+  const int ts = __builtin_ctz(T);   // tiles are 8, 16 or 32 pixels wide
   TileRect r;
-  r.tx0 = (uint32_t)((lohi.x & 0xFFFF) / T);
-  r.ty0 = (uint32_t)(((lohi.x >> 16) & 0xFFFF) / T);
-  r.w = (uint32_t)((lohi.y & 0xFFFF) / T) - r.tx0 + 1;
-  r.h = (uint32_t)(((lohi.y >> 16) & 0xFFFF) / T) - r.ty0 + 1;
+  r.tx0 = (uint32_t)((lohi.x & 0xFFFF) >> ts);
+  r.ty0 = (uint32_t)(((lohi.x >> 16) & 0xFFFF) >> ts);
+  r.w = (uint32_t)((lohi.y & 0xFFFF) >> ts) - r.tx0 + 1;
+  r.h = (uint32_t)(((lohi.y >> 16) & 0xFFFF) >> ts) - r.ty0 + 1;
   return r;
 }
 

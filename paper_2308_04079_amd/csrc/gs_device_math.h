@@ -103,15 +103,18 @@ __device__ __forceinline__ double sqrt_d(double x) {
   return fma(fma(-s, s, x), 0.5 * y, s);
 }
 
-// Unit view direction from the camera centre to the mean (FP64 difference, FP32 result).
+// Unit view direction from the camera centre to the mean: the difference in FP64
+// (the mean and the centre may be far apart and close in value), rounded once to FP32,
+// then normalised in FP32 (the SH colour is evaluated in FP32 anyway; the direction
+// is within a few FP32 ulps). Returns the distance.
 __device__ __forceinline__ float view_dir(const Cam& cam, double x, double y, double z, float* d) {
-  const double ex = x - cam.C[0], ey = y - cam.C[1], ez = z - cam.C[2];
-  const double dist = sqrt_d(ex * ex + ey * ey + ez * ez);
-  const double idist = rcp_d(dist);
-  d[0] = (float)(ex * idist);
-  d[1] = (float)(ey * idist);
-  d[2] = (float)(ez * idist);
-  return (float)dist;
+  const float ex = (float)(x - cam.C[0]), ey = (float)(y - cam.C[1]), ez = (float)(z - cam.C[2]);
+  const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+  const float inv = __builtin_amdgcn_rsqf(r2);
+  d[0] = ex * inv;
+  d[1] = ey * inv;
+  d[2] = ez * inv;
+  return r2 * inv;
 }
 
 // Colour before the clamp, per channel: sum_k sh[k][ch] Y[k] + 0.5, in a fixed
@@ -151,6 +154,7 @@ struct ProjGeom {
   double WM[9];             // W * M, row-major
   double A0[3], A1[3];      // rows of A = J W M (Sigma' = A A^T)
   double a, b, c, det;      // Sigma' = [[a, b], [b, c]], det by Cauchy-Binet
+  double sa, isa;           // sqrt(a) and 1 / sqrt(a) (forward only)
   double u, v;              // projected mean
   int32_t i_lo, i_hi, j_lo, j_hi;
   bool ok;
@@ -174,27 +178,29 @@ __device__ __forceinline__ bool project_covariance(const Cam& cam, const Rules& 
   p.ty = cam_row(cam.R + 3, cam.t[1], x, y, z);
   p.tz = cam_row(cam.R + 6, cam.t[2], x, y, z);
   if (!((float)p.tz >= rules.near_z)) return false;  // near cull on the FP32 depth
+  // fused multiply-adds throughout (written out: the library is built without
+  // contraction); the backward recomputes this with the same instructions
   for (int r = 0; r < 3; ++r)
     for (int c2 = 0; c2 < 3; ++c2)
-      p.WM[r * 3 + c2] = (double)cam.R[r * 3 + 0] * M[0 * 3 + c2] +
-                         (double)cam.R[r * 3 + 1] * M[1 * 3 + c2] +
-                         (double)cam.R[r * 3 + 2] * M[2 * 3 + c2];
+      p.WM[r * 3 + c2] = fma((double)cam.R[r * 3 + 0], M[0 * 3 + c2],
+                             fma((double)cam.R[r * 3 + 1], M[1 * 3 + c2],
+                                 (double)cam.R[r * 3 + 2] * M[2 * 3 + c2]));
   const double fx = cam.fx, fy = cam.fy;
   p.iz = rcp_d(p.tz);
   const double J00 = fx * p.iz, J02 = -fx * p.tx * p.iz * p.iz;
   const double J11 = fy * p.iz, J12 = -fy * p.ty * p.iz * p.iz;
   for (int c2 = 0; c2 < 3; ++c2) {
-    p.A0[c2] = J00 * p.WM[0 * 3 + c2] + J02 * p.WM[2 * 3 + c2];
-    p.A1[c2] = J11 * p.WM[1 * 3 + c2] + J12 * p.WM[2 * 3 + c2];
+    p.A0[c2] = fma(J00, p.WM[0 * 3 + c2], J02 * p.WM[2 * 3 + c2]);
+    p.A1[c2] = fma(J11, p.WM[1 * 3 + c2], J12 * p.WM[2 * 3 + c2]);
   }
-  p.a = p.A0[0] * p.A0[0] + p.A0[1] * p.A0[1] + p.A0[2] * p.A0[2];
-  p.b = p.A0[0] * p.A1[0] + p.A0[1] * p.A1[1] + p.A0[2] * p.A1[2];
-  p.c = p.A1[0] * p.A1[0] + p.A1[1] * p.A1[1] + p.A1[2] * p.A1[2];
+  p.a = fma(p.A0[0], p.A0[0], fma(p.A0[1], p.A0[1], p.A0[2] * p.A0[2]));
+  p.b = fma(p.A0[0], p.A1[0], fma(p.A0[1], p.A1[1], p.A0[2] * p.A1[2]));
+  p.c = fma(p.A1[0], p.A1[0], fma(p.A1[1], p.A1[1], p.A1[2] * p.A1[2]));
   // det(A A^T) = sum of squared 2x2 minors of A (Cauchy-Binet): no a c - b^2 cancellation
-  const double m01 = p.A0[0] * p.A1[1] - p.A0[1] * p.A1[0];
-  const double m02 = p.A0[0] * p.A1[2] - p.A0[2] * p.A1[0];
-  const double m12 = p.A0[1] * p.A1[2] - p.A0[2] * p.A1[1];
-  p.det = m01 * m01 + m02 * m02 + m12 * m12;
+  const double m01 = fma(p.A0[0], p.A1[1], -(p.A0[1] * p.A1[0]));
+  const double m02 = fma(p.A0[0], p.A1[2], -(p.A0[2] * p.A1[0]));
+  const double m12 = fma(p.A0[1], p.A1[2], -(p.A0[2] * p.A1[1]));
+  p.det = fma(m01, m01, fma(m02, m02, m12 * m12));
   return (p.det > 0.0) && isfinite(p.det) && isfinite(p.a) && isfinite(p.c);
 }
 
@@ -209,7 +215,9 @@ __device__ __forceinline__ void project_geometry(const Cam& cam, const Rules& ru
   p.ok = isfinite(p.u) && isfinite(p.v);
   if (!p.ok) return;
   const double ext = (double)rules.ext;
-  const double rx = ext * sqrt_d(p.a), ry = ext * sqrt_d(p.c);
+  p.isa = rsqrt_d(p.a);
+  p.sa = p.a * p.isa;
+  const double rx = ext * p.sa, ry = ext * sqrt_d(p.c);
   // pixel i is covered iff its centre i + 0.5 lies in [u - rx, u + rx]
   const double Wm1 = cam.W - 1, Hm1 = cam.H - 1;
   const double ilo = ceil_clamped(p.u - rx - 0.5, 0.0, Wm1 + 1.0);

@@ -40,8 +40,9 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
   load_sh<K>(sh, n, g, shc);
 #pragma unroll
   for (int k = 0; k < K; ++k) finite = finite && isfinite(shc[k][0] + shc[k][1] + shc[k][2]);
-  const double qn = iso ? 1.0 : sqrt((double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3);
-  const bool alive = finite && qn > 0.0;
+  // |q|^2 and 1/|q| (Newton-refined reciprocal square root, no IEEE divide or sqrt)
+  const double qq = iso ? 1.0 : fma((double)q0, q0, fma((double)q1, q1, fma((double)q2, q2, (double)q3 * q3)));
+  const bool alive = finite && qq > 0.0;
   double M[9];
   double opac = 0.0;
   if (alive) {
@@ -53,7 +54,7 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
       R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.0;
       s0 = s1 = s2 = exp((((double)ls0 + (double)ls1) + (double)ls2) / 3.0);
     } else {
-      const double iq = 1.0 / qn;
+      const double iq = rsqrt_d(qq);
       quat_to_rot(q0 * iq, q1 * iq, q2 * iq, q3 * iq, R);
       s0 = exp((double)ls0);
       s1 = exp((double)ls1);
@@ -86,12 +87,12 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
     const float r = fmaxf(sh_colour_raw<K>(shc, Y, 0), 0.0f);
     const float gc = fmaxf(sh_colour_raw<K>(shc, Y, 1), 0.0f);
     const float b = fmaxf(sh_colour_raw<K>(shc, Y, 2), 0.0f);
-    const int T = views.tile;
-    tiles_touched[idx] = (p.i_hi / T - p.i_lo / T + 1) * (p.j_hi / T - p.j_lo / T + 1);
+    const int ts = __builtin_ctz(views.tile);   // tiles are 8, 16 or 32 pixels wide
+    tiles_touched[idx] = ((p.i_hi >> ts) - (p.i_lo >> ts) + 1) * ((p.j_hi >> ts) - (p.j_lo >> ts) + 1);
     const float z32 = (float)p.tz;
     depth_key[idx] = __float_as_uint(z32);
     // whitening L^-1 of Sigma' = L L^T: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
-    const double sa = sqrt_d(p.a), isa = rcp_d(sa), isd = rsqrt_d(p.det);
+    const double sa = p.sa, isa = p.isa, isd = rsqrt_d(p.det);
     const double w00 = isa, w10 = -p.b * isa * isd, w11 = sa * isd;
     // whitened offset of the box's corner pixel centre from the mean, c = L^-1 (p0 - mean):
     // a pixel at p0 + D then has whitened offset L^-1 D + c, whose FP32 evaluation errs
@@ -127,12 +128,14 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   const double x = means[g], y = means[n + g], z = means[2 * n + g];
   float dmu_f[3] = {0.0f, 0.0f, 0.0f};
   {
-  double dmu[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0};
+  double ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0};
   double dop = 0.0, opac = 0.0;
   const bool iso = rules.isotropic != 0;
   if (any) {
     double qh[4] = {1.0, 0.0, 0.0, 0.0}, iq = 1.0;
-    double R[9], M[9];
+    double M[9];
+    {
+    double R[9];
     if (iso) {
       R[0] = R[4] = R[8] = 1.0;
       R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.0;
@@ -140,8 +143,7 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
                                (double)log_scales[2 * n + g]) / 3.0);
     } else {
       const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
-      const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-      iq = 1.0 / qn;
+      iq = rsqrt_d(fma(q0, q0, fma(q1, q1, fma(q2, q2, q3 * q3))));
       qh[0] = q0 * iq;
       qh[1] = q1 * iq;
       qh[2] = q2 * iq;
@@ -153,8 +155,11 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
     }
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * s[c];
+    }
     opac = 1.0 / (1.0 + exp(-(double)logits[g]));
-    double dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // the view loop accumulates in FP32 (the gradients' own precision); every
+    // per-view term is formed in FP64
+    float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int v = 0; v < views.n_views; ++v) {
       const int64_t idx = (int64_t)v * n + g;
       if (tiles_touched[idx] <= 0) continue;
@@ -182,22 +187,20 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
       const double fx = cam.fx, fy = cam.fy, tx = p.tx, ty = p.ty;
       const double iz = p.iz, iz2 = iz * iz, iz3 = iz2 * iz;
       const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
-      double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0, dWM[9];
+      double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
       for (int k = 0; k < 3; ++k) {
         dJ00 += dA0[k] * p.WM[0 * 3 + k];
         dJ02 += dA0[k] * p.WM[2 * 3 + k];
         dJ11 += dA1[k] * p.WM[1 * 3 + k];
         dJ12 += dA1[k] * p.WM[2 * 3 + k];
-        dWM[0 * 3 + k] = J00 * dA0[k];
-        dWM[1 * 3 + k] = J11 * dA1[k];
-        dWM[2 * 3 + k] = J02 * dA0[k] + J12 * dA1[k];
       }
-      // WM = W M  ->  dM += W^T dWM
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          dM[i * 3 + j] += (double)cam.R[0 * 3 + i] * dWM[0 * 3 + j] +
-                           (double)cam.R[1 * 3 + i] * dWM[1 * 3 + j] +
-                           (double)cam.R[2 * 3 + i] * dWM[2 * 3 + j];
+      // A = U M with U = J W (rows U0 = J00 W0 + J02 W2, U1 = J11 W1 + J12 W2):
+      // dM += U^T dA
+      for (int i = 0; i < 3; ++i) {
+        const double u0 = J00 * (double)cam.R[0 * 3 + i] + J02 * (double)cam.R[2 * 3 + i];
+        const double u1 = J11 * (double)cam.R[1 * 3 + i] + J12 * (double)cam.R[2 * 3 + i];
+        for (int j = 0; j < 3; ++j) dM[i * 3 + j] += (float)(u0 * dA0[j] + u1 * dA1[j]);
+      }
       // camera-space mean through (u, v) and J
       const double dtx = du * fx * iz + dJ02 * (-fx * iz2);
       const double dty = dv * fy * iz + dJ12 * (-fy * iz2);
@@ -205,10 +208,18 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
                          dJ02 * (2.0 * fx * tx * iz3) + dJ11 * (-fy * iz2) +
                          dJ12 * (2.0 * fy * ty * iz3);
       for (int k = 0; k < 3; ++k)
-        dmu[k] += (double)cam.R[0 * 3 + k] * dtx + (double)cam.R[1 * 3 + k] * dty +
-                  (double)cam.R[2 * 3 + k] * dtz;
+        dmu_f[k] += (float)((double)cam.R[0 * 3 + k] * dtx + (double)cam.R[1 * 3 + k] * dty +
+                            (double)cam.R[2 * 3 + k] * dtz);
     }
-    // M = R diag(s): dR_ij = dM_ij s_j, ds_j = sum_i dM_ij R_ij
+    // M = R diag(s): dR_ij = dM_ij s_j, ds_j = sum_i dM_ij R_ij (R recomputed here
+    // rather than held through the view loop)
+    double R[9];
+    if (iso) {
+      R[0] = R[4] = R[8] = 1.0;
+      R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.0;
+    } else {
+      quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
+    }
     double dR[9];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -239,9 +250,6 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   d_log_scales[2 * n + g] = (float)(ds[2] * s[2]);
   for (int c = 0; c < 4; ++c) d_quats[(int64_t)c * n + g] = (float)dq[c];
   d_logits[g] = (float)(dop * opac * (1.0 - opac));
-  dmu_f[0] = (float)dmu[0];
-  dmu_f[1] = (float)dmu[1];
-  dmu_f[2] = (float)dmu[2];
   }
   // SH colour: coefficient gradients and the view-direction term of the mean. The
   // barrier keeps the coefficient loads from being hoisted into the geometry loop.
