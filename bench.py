@@ -52,9 +52,15 @@ def parse():
     ap.add_argument("--workload", choices=("train4", "full1080", "multiview"), default="train4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
-    ap.add_argument("--mode", choices=("views", "train"), default="views",
+    ap.add_argument("--mode", choices=("views", "train", "oracle"), default="views",
                     help="views: the fwd+bwd views/s metric (default); train: the Adam training "
-                         "loop over 4-view minibatches (steps/s and peak HBM)")
+                         "loop over 4-view minibatches (steps/s and peak HBM); oracle: the CPU "
+                         "oracle's seconds per view on the parity workloads (no GPU)")
+    ap.add_argument("--tile", type=int, default=None, help="tile size (default: autotuned)")
+    ap.add_argument("--lds-batch", type=int, default=None,
+                    help="list entries staged per wave and round (default: autotuned)")
+    ap.add_argument("--digit-bits", type=int, default=None,
+                    help="radix digit width of the sorts (default: autotuned)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -68,6 +74,11 @@ def main():
         sys.exit(2)
     if args.mode == "train":
         return train(args)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.mode == "oracle":
+        return oracle_table(log)
+    # the oracle runs first, in worker processes forked before this process touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(log)
     import numpy as np
     import torch
 
@@ -78,7 +89,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
 
     t0 = time.time()
     sc, cams = scenes.workload(args.workload, args.n)
@@ -91,10 +101,25 @@ def main():
     V = len(cams)
     log(f"[bench] scene ready in {time.time() - t0:.1f}s: N={sc.n}, {V} views")
 
-    rast = Rasterizer(sh_degree=sc.sh_degree)
-    tstate = rast.render(tparams, cams)             # sizes the capacity and renders targets
-    target = tstate.image.clone()
+    knobs = {k: v for k, v in (("tile_size", args.tile), ("lds_batch", args.lds_batch),
+                               ("sort_digit_bits", args.digit_bits)) if v is not None}
+    tstate = Rasterizer(sh_degree=sc.sh_degree, **knobs).render(tparams, cams)
+    target = tstate.image.clone()                   # the targets do not depend on the knobs
     del tstate, tparams
+    tuned = None
+    if len(knobs) < 3:
+        # the autotuner times one fwd + L1 + bwd step per combination of the knobs not
+        # given on the command line, on this workload
+        from paper_2308_04079_amd.autotune import DIGIT_BITS, LDS_BATCHES, TILE_SIZES, autotune
+        t0 = time.time()
+        tuned = autotune(params, cams, target, steps=2, use_cache=False,
+                         tile_sizes=(knobs["tile_size"],) if "tile_size" in knobs else TILE_SIZES,
+                         lds_batches=(knobs["lds_batch"],) if "lds_batch" in knobs else LDS_BATCHES,
+                         digit_bits=(knobs["sort_digit_bits"],) if "sort_digit_bits" in knobs
+                         else DIGIT_BITS)
+        knobs = {k: tuned[k] for k in ("tile_size", "lds_batch", "sort_digit_bits")}
+        log(f"[bench] autotune ({len(tuned['trials'])} trials, {time.time() - t0:.0f}s): {knobs}")
+    rast = Rasterizer(sh_degree=sc.sh_degree, **knobs)
     probe = rast.render(params, cams)
     st, count = probe.read_status()
     rast.capacity = int(count * 1.15) + 4096
@@ -150,7 +175,7 @@ def main():
 
     per_view = per_view_graph = None
     if not args.no_per_view:
-        prast = Rasterizer(sh_degree=sc.sh_degree, capacity=rast.capacity)
+        prast = Rasterizer(sh_degree=sc.sh_degree, capacity=rast.capacity, **knobs)
         tviews = [target[3 * state.pix_offset[v]:3 * state.pix_offset[v + 1]] for v in range(V)]
 
         def per_view_step():
@@ -185,7 +210,6 @@ def main():
     hbm = hbm_rates(stages["ms"], stages["state"], count, sc.n, V, (sc.sh_degree + 1) ** 2,
                     rast.cfg.sort_digit_bits)
     q = np.percentile(np.array(step_ms), [10, 50, 90])
-    cpu = None if args.no_cpu_baseline else cpu_baseline(log)
 
     out = {
         "metric": "1080p fwd+bwd views/sec at 3M Gaussians, batched vs per-view, <=1e-4 image err",
@@ -203,7 +227,8 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(n=sc.n, v=V),
                    "gaussians": sc.n, "views_per_step": V,
                    "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
-                   "tile": 16, "sort_digit_bits": 8, "lds_batch": 64, "instances": count},
+                   "tile": rast.cfg.tile_size, "sort_digit_bits": rast.cfg.sort_digit_bits,
+                   "lds_batch": rast.cfg.lds_batch, "instances": count},
         "batched_eager_value": round(eager_views, 3),
         "per_view_value": None if per_view is None else round(per_view, 3),
         "per_view_graph_value": None if per_view_graph is None else round(per_view_graph, 3),
@@ -212,6 +237,9 @@ def main():
         "stage_hbm": hbm,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "autotune": None if tuned is None else {
+            "chosen": knobs, "trials": [{k: (round(v, 4) if k == "ms" else v) for k, v in t.items()}
+                                        for t in tuned["trials"]]},
     }
     print(json.dumps(out), flush=True)
 
@@ -220,9 +248,10 @@ def train(args):
     """The optimisation loop of Alg. 1 on the library: 3M Gaussians, SH3, 4 distinct
     1920x1080 views per step drawn (seeded) from a pool of 64 orbit cameras, the
     L1 + 0.2 D-SSIM loss against targets rendered once from a jittered copy of the
-    scene, Adam on every parameter group, density statistics accumulated every step.
-    Warm-up resolution and the SH ramp are off (full resolution, all bands) and no
-    densification falls inside the timed steps, so every step does the same work."""
+    scene, Adam on every parameter group, density statistics accumulated every step and
+    density control (clone, split, prune) every 100 iterations, inside the timed steps.
+    Warm-up resolution and the SH ramp are off (full resolution, all bands); no opacity
+    reset falls within 200 steps (its cadence is 3000)."""
     import numpy as np
     import torch
 
@@ -240,17 +269,21 @@ def train(args):
     del tparams
     total = args.warmup + args.steps
     cfg = TrainConfig(iterations=total, views_per_step=4, warmup=(0, 0), sh_every=0,
-                      densify_from=total + 1, densify_until=total, reset_every=10 ** 9)
+                      densify_from=1, densify_until=total)
     tr = Trainer(GaussianParams.from_numpy(sc, dev), pool, targets, extent=20.0, cfg=cfg)
     for _ in range(args.warmup):
         tr.step()
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats(dev)
+    n_start = tr.params.n
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         tr.step()
+        if (k + 1) % 50 == 0:
+            log(f"[train] step {k + 1}: {tr.params.n} Gaussians")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    n_densify = sum(1 for it in range(args.warmup + 1, total + 1) if tr.densify_now(it))
     losses = [float(x.sum()) for x in tr.history[args.warmup:]]
     log(f"[train] {args.steps} steps in {dt:.2f}s, loss {losses[0]:.5f} -> {losses[-1]:.5f}")
     print(json.dumps({
@@ -261,8 +294,11 @@ def train(args):
         "data": "synthetic",
         "config": {"workload": f"clustered scene, {sc.n} Gaussians, SH3, Adam over 4 of 64 "
                                "orbit 1920x1080 views per step, L1 + 0.2 D-SSIM loss, "
-                               "density statistics",
+                               "density statistics every step and density control every "
+                               "100 iterations",
                    "gaussians": sc.n, "views_per_step": 4},
+        "gaussians_timed_start": n_start, "gaussians_timed_end": tr.params.n,
+        "densifications_timed": n_densify,
         "peak_hbm_bytes": int(torch.cuda.max_memory_allocated(dev)),
         "loss_first": losses[0], "loss_last": losses[-1]}), flush=True)
 
@@ -352,94 +388,116 @@ def measured_traffic(kernel):
     return rec["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
-def processed_pairs(st, cfg, T=16):
-    """(wave, Gaussian) pairs the blend-backward launch evaluates.
+def backward_work(st, cfg):
+    """Work units of one gs_render_bwd launch, counted from the sorted instances and the
+    forward state outside the timed region.
 
-    A wave owns an 8x8 pixel block of a tile; it walks the tile's list from the
-    block's last contributor back to the start and evaluates (on all 64 lanes)
-    every entry whose 3-sigma pixel box meets its block and whose least Mahalanobis
-    distance m over the block's pixel-centre rectangle is within
-    min(9, 2 ln(o / alpha_min)) (the kernel's two staging tests, replayed here in
-    FP64 without the kernel's rounding slack).
+    The kernel runs one 64-lane wave per 8x8 pixel block of a tile. A wave walks its
+    tile's list back to front from the largest last contributor of its pixels and
+    evaluates, on all 64 lanes, every entry at or before that position whose pixel box
+    meets the block and whose least Mahalanobis distance m over the block's pixel
+    centres is within min(ext^2, 2 ln(o / alpha_min)) (the kernel's staging tests,
+    replayed here in FP64 without the kernel's rounding slack). Each such step also
+    sums the nine gradient terms over the wave once.
+
+    Returns {"steps" (= wave-Gaussian pairs, each one nine-value wave reduction),
+    "lane_evaluations" (= 64 x steps), "algorithmic_evaluations" (every (pixel, list
+    entry) pair up to the pixel's last contributor: the method's own count)}.
     """
     import torch
+    T = cfg.tile_size
+    nb = T // 8                                     # 8x8 blocks per tile side
     dev = st.ranges.device
     M = int(st.count.item())
     vals = st.vals[:M].long() & 0xFFFFFFFF
     tile = st.tile_ids(cfg)[:M].long()
-    rec = st.record.view(-1, 12)
-    lo = rec[vals, 0].view(torch.int32).long()
-    hi = rec[vals, 1].view(torch.int32).long()
+    rec = st.record.view(-1, 12)[vals]
+    lo = rec[:, 0].view(torch.int32).long()
+    hi = rec[:, 1].view(torch.int32).long()
     ilo, jlo, ihi, jhi = lo & 0xFFFF, (lo >> 16) & 0xFFFF, hi & 0xFFFF, (hi >> 16) & 0xFFFF
-    mx, my = rec[vals, 2].double(), rec[vals, 3].double()
-    w00, w10, w11 = rec[vals, 4].double(), rec[vals, 5].double(), rec[vals, 6].double()
-    opac = rec[vals, 7].double()
-    thr_all = torch.clamp(2.0 * (torch.log(opac) - math.log(cfg.alpha_min)), max=cfg.sigma_extent ** 2)
+    c0, c1 = rec[:, 2].double(), rec[:, 3].double()
+    w00, w10, w11, opac = (rec[:, k].double() for k in (4, 5, 6, 7))
+    del rec
+    thr = torch.clamp(2.0 * (torch.log(opac) - math.log(cfg.alpha_min)), max=cfg.sigma_extent ** 2)
     pos = torch.arange(M, device=dev)
+    ranges = st.ranges.view(-1, 2).long()
     toff = torch.tensor(st.tile_offset, device=dev)
     view = torch.searchsorted(toff, tile, right=True) - 1
-    total = 0
-    for v in range(st.n_views):
-        cam = st.cams[v]
+    Wv = torch.tensor([c.width for c in st.cams], device=dev)[view]
+    Hv = torch.tensor([c.height for c in st.cams], device=dev)[view]
+    txn = (Wv + T - 1) // T
+    lt = tile - toff[view]
+    tx, ty = lt % txn, lt // txn
+    # per (tile, 8x8 block): the largest last contributor of its pixels, capped at the
+    # tile's last instance (-1 if no pixel blended anything)
+    blk_last = torch.full((st.n_tiles, nb * nb), -1, dtype=torch.long, device=dev)
+    algo = 0
+    for v, cam in enumerate(st.cams):
         W, H = cam.width, cam.height
-        tx_n, ty_n = (W + T - 1) // T, (H + T - 1) // T
+        txv, tyv = (W + T - 1) // T, (H + T - 1) // T
         last = st.view_plane(st.last_idx, v).long()
-        # per 8x8 block: the largest last index (-1 if none)
-        Hp, Wp = ty_n * T, tx_n * T
-        pad = torch.full((Hp, Wp), -1, dtype=torch.long, device=dev)
+        pad = torch.full((tyv * T, txv * T), -1, dtype=torch.long, device=dev)
         pad[:H, :W] = last
-        blk = pad.view(Hp // 8, 8, Wp // 8, 8).amax(dim=(1, 3))          # (Hp/8, Wp/8)
-        sel = view == v
-        t_local = tile[sel] - st.tile_offset[v]
-        tyi, txi = t_local // tx_n, t_local % tx_n
-        for qy in range(T // 8):
-            for qx in range(T // 8):
-                by, bx = tyi * (T // 8) + qy, txi * (T // 8) + qx
-                x0, y0 = bx * 8, by * 8
-                inside = (x0 < W) & (y0 < H)
-                x1, y1 = torch.clamp(x0 + 7, max=W - 1), torch.clamp(y0 + 7, max=H - 1)
-                ov = (ilo[sel] <= x1) & (ihi[sel] >= x0) & (jlo[sel] <= y1) & (jhi[sel] >= y0)
-                dxa = (x0 - ilo[sel]) + 0.5 - mx[sel]
-                dxb = (x1 - ilo[sel]) + 0.5 - mx[sel]
-                dya = (y0 - jlo[sel]) + 0.5 - my[sel]
-                dyb = (y1 - jlo[sel]) + 0.5 - my[sel]
-                a00, a10, a11 = w00[sel], w10[sel], w11[sel]
+        b8 = pad.view(tyv, nb, 8, txv, nb, 8).amax(dim=(2, 5))           # (tyv, nb, txv, nb)
+        b8 = b8.permute(0, 2, 1, 3).reshape(tyv * txv, nb * nb)
+        t0 = st.tile_offset[v]
+        blk_last[t0:t0 + tyv * txv] = torch.minimum(b8, ranges[t0:t0 + tyv * txv, 1:2] - 1)
+        # algorithmic: every list entry up to each pixel's last contributor
+        tstart = ranges[t0:t0 + tyv * txv, 0].view(tyv, 1, txv, 1).expand(tyv, T, txv, T)
+        tstart = tstart.reshape(tyv * T, txv * T)[:H, :W]
+        algo += int(torch.clamp(last - tstart + 1, min=0).sum().item())
+    ax = -c0 / w00                                  # the mean's offset from the corner centre
+    ay = -(w10 * ax + c1) / w11
+    steps = 0
+    for b in range(nb * nb):
+        bx, by = b % nb, b // nb
+        x0, y0 = tx * T + 8 * bx, ty * T + 8 * by
+        x1, y1 = torch.minimum(x0 + 7, Wv - 1), torch.minimum(y0 + 7, Hv - 1)
+        ok = (x0 < Wv) & (y0 < Hv) & (ilo <= x1) & (ihi >= x0) & (jlo <= y1) & (jhi >= y0)
+        xa, xb = (x0 - ilo).double(), (x1 - ilo).double()
+        ya, yb = (y0 - jlo).double(), (y1 - jlo).double()
 
-                def edge_x(X):   # least m on the edge dx = X: vertex of the parabola, clamped
-                    dy = torch.minimum(torch.maximum(-a10 * X / a11, dya), dyb)
-                    return (a00 * X) ** 2 + (a10 * X + a11 * dy) ** 2
+        def edge_x(X):      # least m on the edge Dx = X
+            dj = torch.clamp(-(w10 * X + c1) / w11, min=ya, max=yb)
+            return (w00 * X + c0) ** 2 + (w10 * X + w11 * dj + c1) ** 2
 
-                def edge_y(Y):
-                    dx = torch.minimum(torch.maximum(-a10 * a11 * Y / (a00 ** 2 + a10 ** 2), dxa), dxb)
-                    return (a00 * dx) ** 2 + (a10 * dx + a11 * Y) ** 2
+        def edge_y(Y):      # least m on the edge Dy = Y
+            di = -(w00 * c0 + w10 * (w11 * Y + c1)) / (w00 ** 2 + w10 ** 2)
+            di = torch.minimum(torch.maximum(di, xa), xb)
+            return (w00 * di + c0) ** 2 + (w10 * di + w11 * Y + c1) ** 2
 
-                mmin = torch.minimum(torch.minimum(edge_x(dxa), edge_x(dxb)),
-                                     torch.minimum(edge_y(dya), edge_y(dyb)))
-                inside_rect = (dxa <= 0) & (dxb >= 0) & (dya <= 0) & (dyb >= 0)
-                mmin = torch.where(inside_rect, torch.zeros_like(mmin), mmin)
-                ov &= mmin <= thr_all[sel]
-                wl = blk[by.clamp(max=blk.shape[0] - 1), bx.clamp(max=blk.shape[1] - 1)]
-                total += int((inside & ov & (pos[sel] <= wl)).sum().item())
-    return total
+        inside = (ax >= xa) & (ax <= xb) & (ay >= ya) & (ay <= yb)
+        mmin = torch.minimum(torch.minimum(edge_x(xa), edge_x(xb)),
+                             torch.minimum(edge_y(ya), edge_y(yb)))
+        mmin = torch.where(inside, torch.zeros_like(mmin), mmin)
+        ok &= (mmin <= thr) & (pos <= blk_last[tile, b])
+        steps += int(ok.sum().item())
+    return {"steps": steps, "lane_evaluations": 64 * steps, "algorithmic_evaluations": algo}
 
 
 def roofline(stages, state, count, n, V, cfg):
-    """Roofline of the dominant kernel. For the blend kernels (VALU bound): lane
-    evaluations actually issued (processed pairs x 64) x the arithmetic of one
-    evaluation (FWD_OPS_PER_EVAL, BWD_OPS_PER_EVAL), against the FP32 VALU peak."""
+    """Roofline of the dominant kernel. For the backward blend (VALU bound): the lane
+    evaluations the launch issues (backward_work) x the FP32 arithmetic of one
+    evaluation (BWD_OPS_PER_EVAL), over the launch's event-timed duration, against the
+    FP32 VALU peak; the method's own evaluation count beside it as
+    ``algorithmic_frac``. For a streaming kernel: its algorithmic bytes over HBM peak."""
     ms = stages["ms"]
     dom = max(("render_fwd", "render_bwd", "project", "project_bwd", "sort"), key=lambda k: ms[k])
     st = stages["state"]
-    if dom in ("render_bwd", "render_fwd"):
-        pairs = processed_pairs(st, cfg)
-        ops = BWD_OPS_PER_EVAL if dom == "render_bwd" else FWD_OPS_PER_EVAL
-        lane_evals = pairs * 64
-        achieved = lane_evals * ops / (ms[dom] * 1e-3) / 1e12
+    if dom == "render_bwd":
+        wk = backward_work(st, cfg)
+        sec = ms[dom] * 1e-3
+        achieved = wk["lane_evaluations"] * BWD_OPS_PER_EVAL / sec / 1e12
+        algo = wk["algorithmic_evaluations"] * BWD_OPS_PER_EVAL / sec / 1e12
         return {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s (FP32 VALU lane-ops)",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(dom),
-                "units": {"wave_gaussian_pairs": pairs, "lane_evaluations": lane_evals,
-                          "ops_per_evaluation": ops}}
+                "duration_ms": round(ms[dom], 4),
+                "units": {**wk, "ops_per_evaluation": BWD_OPS_PER_EVAL},
+                "algorithmic_frac": round(algo / VALU_PEAK_TOPS, 4)}
+    if dom == "render_fwd":
+        return {"kernel": dom, "bound": "alu", "achieved": None, "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s (FP32 VALU lane-ops)", "frac": None, "traffic": None}
     K = 16
     per = {"project": (4 * (11 + 3 * K) + 56 * V), "project_bwd": (4 * (11 + 3 * K) * 2 + 40 * V)}
     b = per.get(dom, 24) * (n if dom in per else count)
@@ -478,67 +536,200 @@ def hbm_rates(ms, st, count, n, V, K, digit_bits):
     return out
 
 
-# FP32 VALU operations of one (pixel, Gaussian) evaluation as the method states it
-# (one op per add, mul, fma, compare, select, min, exp, reciprocal). Forward, 22:
-# offset 4, Mahalanobis 5, exp argument and exp 2, alpha 2, three tests 3, T' 2,
-# weight and colour accumulation 4. Backward, 57: the forward's 16 evaluation ops,
-# T recovery 3, colour gradient 4, alpha gradient 10, back-to-front accumulator 3,
-# clamp test 2, opacity / mean / whitening gradients 10, and the 9 adds that sum the
-# pixel's nine partial gradients into the Gaussian's totals (the accumulation the
-# forward's count includes for the colour).
-FWD_OPS_PER_EVAL = 22
-BWD_OPS_PER_EVAL = 57
+# FP32 VALU operations of one (pixel, Gaussian) evaluation of the backward blend, as the
+# method states it (one op per add, mul, fma, compare, select, min, exp, reciprocal):
+# about 40 arithmetic ops plus one exp and one reciprocal. The nine-value reduction of
+# a step's gradients over the wave is its own unit (one per step), not counted per
+# evaluation.
+BWD_OPS_PER_EVAL = 42
+
+
+# ---------------------------------------------------------------------------
+# the FP64 oracle timed on the host cores (the reported CPU baseline)
+# ---------------------------------------------------------------------------
+
+_ORACLE = {}   # scene, projection and tile lists, shared with forked worker processes
+
+
+def _oracle_gaussian_chunk(bounds):
+    """Worker: projection and projection backward of one slice of the Gaussians (the
+    per-Gaussian phases; their cost does not depend on the gradient values)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.adjoint import empty_acc, project_backward
+    from oracle.gaussians import project
+    lo, hi = bounds
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        sub = _ORACLE["scene"].subset(slice(lo, hi))
+        p = project(sub, _ORACLE["cam"], _ORACLE["rules"])
+        if not _ORACLE["fwd_only"]:
+            project_backward(sub, p, empty_acc(p.n))
+        return time.perf_counter() - t
+
+
+def _oracle_tile_chunk(tiles):
+    """Worker: blend (forward, or forward + adjoint) of the listed tiles; returns the
+    seconds of each."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.adjoint import blend_backward, empty_acc
+    from oracle.raster import blend, tile_pixels
+    p, tl, r = _ORACLE["proj"], _ORACLE["lists"], _ORACLE["rules"]
+    cam = _ORACLE["cam"]
+    out = []
+    with threadpool_limits(limits=1):
+        rng = np.random.default_rng(int(tiles[0]) if len(tiles) else 0)
+        acc = empty_acc(p.n)
+        for tt in tiles:
+            t = time.perf_counter()
+            px, py = tile_pixels(int(tt), tl, cam.width, cam.height, r.tile)
+            ids = tl.ids[tl.start[tt]:tl.start[tt + 1]]
+            if _ORACLE["fwd_only"]:
+                blend(p, ids, px, py, r)
+            else:
+                blend_backward(p, ids, px, py, rng.standard_normal((len(px), 3)), r, acc)
+            out.append(time.perf_counter() - t)
+    return out
+
+
+def stratified_tiles(lengths, n_sample, rng):
+    """A seeded sample of n_sample tiles stratified by list length: the tiles sorted by
+    length are cut into n_sample strata of (nearly) equal size and one tile is drawn
+    from each; returns (tiles, stratum sizes). Sum over the sample of stratum size x
+    per-tile cost estimates the frame's cost without bias, with far less variance than
+    a plain random sample of the heavy-tailed tile costs."""
+    import numpy as np
+    order = np.argsort(lengths, kind="stable")
+    edges = np.linspace(0, len(order), n_sample + 1).astype(np.int64)
+    tiles, weights = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        if b > a:
+            tiles.append(int(order[rng.integers(a, b)]))
+            weights.append(int(b - a))
+    return np.array(tiles, dtype=np.int64), np.array(weights, dtype=np.float64)
+
+
+def oracle_view_seconds(sc, cam, procs, tiles_per_proc, fwd_only=False, seed=0):
+    """Seconds the oracle takes for one view, on `procs` processes of one thread each.
+
+    Per-Gaussian phases (projection, projection backward) are split over the processes
+    by Gaussian slices; the tile lists (one global stable sort) run in one process; the
+    blend is timed on a seeded sample of procs * tiles_per_proc tiles (every tile when
+    the view has no more), stratified by list length, and scaled to the frame.
+    Returns the phase times."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.gaussians import project
+    from oracle.raster import tile_lists
+    from oracle.rules import Rules
+    r = Rules()
+    _ORACLE.update(scene=sc, cam=cam, rules=r, fwd_only=fwd_only)
+    ctx = mp.get_context("fork")
+    bounds = np.linspace(0, sc.n, procs + 1).astype(np.int64)
+    chunks = [(int(bounds[i]), int(bounds[i + 1])) for i in range(procs)]
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        if procs == 1:
+            _oracle_gaussian_chunk(chunks[0])
+        else:
+            with ctx.Pool(procs) as pool:
+                pool.map(_oracle_gaussian_chunk, chunks)
+        t_gauss = time.perf_counter() - t
+        p = project(sc, cam, r)           # the parent's copy for the lists and the blend
+        t = time.perf_counter()
+        tl = tile_lists(p, r)
+        t_lists = time.perf_counter() - t
+    _ORACLE.update(proj=p, lists=tl)
+    n_tiles = tl.tiles_x * tl.tiles_y
+    n_sample = min(n_tiles, procs * tiles_per_proc)
+    sample, weight = stratified_tiles(np.diff(tl.start), n_sample,
+                                      np.random.default_rng(seed))
+    parts = [np.arange(i, len(sample), procs) for i in range(procs)]
+    t = time.perf_counter()
+    if procs == 1:
+        per_tile = [_oracle_tile_chunk(sample)]
+    else:
+        with ctx.Pool(procs) as pool:
+            per_tile = pool.map(_oracle_tile_chunk, [sample[k] for k in parts])
+    t_tiles = time.perf_counter() - t
+    _ORACLE.clear()
+    secs = np.zeros(len(sample))
+    for k, ts in zip(parts, per_tile):
+        secs[k] = ts
+    # frame estimate: the stratified sum of per-tile seconds, run at the parallel
+    # efficiency the sample itself reached on `procs` processes
+    frame_cpu = float((secs * weight).sum())
+    t_blend = frame_cpu * t_tiles / max(float(secs.sum()), 1e-12) if procs > 1 else frame_cpu
+    return {"per_gaussian_s": t_gauss, "lists_s": t_lists, "blend_sample_s": t_tiles,
+            "blend_s": t_blend, "tiles_sampled": int(len(sample)), "tiles": int(n_tiles),
+            "view_s": t_gauss + t_lists + t_blend}
+
+
+def oracle_procs():
+    """Worker processes for the multi-process oracle timing: one per host core, at most
+    16 (the host share of one GPU)."""
+    return max(1, min(os.cpu_count() or 1, 16))
 
 
 def cpu_baseline(log):
-    """The FP64 oracle timed on a bounded sample of one view of the same workload, with
-    NumPy's thread pools held to one thread (``cores`` = 1)."""
-    from threadpoolctl import threadpool_limits
-
+    """The FP64 oracle on one view of the benchmark workload (3M Gaussians, 1920x1080,
+    fwd+bwd), at one process and at one process per host core, each process holding
+    NumPy's thread pools to one thread. ``value`` / ``cores`` are the multi-process
+    figure; ``value_1_process`` the single-process one."""
     import scenes
-    from oracle.rules import Rules
+    sc, cams = scenes.workload("train4")
+    cam = cams[0]
+    P = oracle_procs()
+    one = oracle_view_seconds(sc, cam, 1, 48)
+    log(f"[bench] oracle, 1 process: {one['view_s']:.0f} s per view "
+        f"(per-Gaussian {one['per_gaussian_s']:.1f} s, lists {one['lists_s']:.1f} s, "
+        f"{one['tiles_sampled']} tiles {one['blend_sample_s']:.1f} s)")
+    multi = one
+    if P > 1:
+        multi = oracle_view_seconds(sc, cam, P, 16)
+        log(f"[bench] oracle, {P} processes: {multi['view_s']:.0f} s per view "
+            f"(per-Gaussian {multi['per_gaussian_s']:.1f} s, lists {multi['lists_s']:.1f} s, "
+            f"{multi['tiles_sampled']} tiles {multi['blend_sample_s']:.1f} s)")
+    return {"value": round(1.0 / multi["view_s"], 6), "unit": "views/s", "cores": P,
+            "kind": "oracle",
+            "value_1_process": round(1.0 / one["view_s"], 6),
+            "sample": f"one 1920x1080 view of the 3M-Gaussian workload, fwd+bwd: projection and "
+                      f"projection backward of every Gaussian split over {P} processes, tile "
+                      f"lists in one, fwd+bwd blend of {multi['tiles_sampled']} seeded tiles of "
+                      f"{multi['tiles']} (stratified by list length) scaled to the frame at "
+                      f"the sample's parallel efficiency; value_1_process: the "
+                      f"same in one process with {one['tiles_sampled']} tiles; NumPy FP64, "
+                      f"one thread per process"}
 
-    sc = scenes.clustered_scene(3_000_000, 4, 3)
-    cam = scenes.orbit_cameras(1, 4, resolutions=((1920, 1080),))[0]
-    r = Rules()
-    with threadpool_limits(limits=1):       # BLAS and OpenMP pools: one thread
-        return _cpu_baseline_timed(sc, cam, r, log)
 
-
-def _cpu_baseline_timed(sc, cam, r, log):
-    import numpy as np
-
-    from oracle.adjoint import blend_backward, empty_acc, project_backward
-    from oracle.gaussians import project
-    from oracle.raster import tile_lists, tile_pixels
-    t = time.perf_counter()
-    p = project(sc, cam, r)
-    t_proj = time.perf_counter() - t
-    t = time.perf_counter()
-    tl = tile_lists(p, r)
-    t_lists = time.perf_counter() - t
-    n_tiles = tl.tiles_x * tl.tiles_y
-    rng = np.random.default_rng(0)
-    sample = rng.choice(n_tiles, 16, replace=False)
-    acc = empty_acc(p.n)
-    w = rng.standard_normal((cam.height, cam.width, 3))
-    t = time.perf_counter()
-    for tt in sample:
-        px, py = tile_pixels(int(tt), tl, cam.width, cam.height, r.tile)
-        ids = tl.ids[tl.start[tt]:tl.start[tt + 1]]
-        blend_backward(p, ids, px, py, w[py, px], r, acc)
-    t_tiles = time.perf_counter() - t
-    t = time.perf_counter()
-    project_backward(sc, p, acc)
-    t_pbwd = time.perf_counter() - t
-    per_view_s = t_proj + t_lists + t_tiles * n_tiles / len(sample) + t_pbwd
-    log(f"[bench] oracle: project {t_proj:.1f}s lists {t_lists:.1f}s "
-        f"{len(sample)} tiles fwd+bwd {t_tiles:.1f}s project_bwd {t_pbwd:.1f}s "
-        f"-> {per_view_s:.0f}s per view")
-    return {"value": round(1.0 / per_view_s, 6), "unit": "views/s", "cores": 1, "kind": "oracle",
-            "sample": f"one 1920x1080 view of the 3M-Gaussian workload: full projection, tile "
-                      f"lists and projection backward, fwd+bwd blend of {len(sample)} of "
-                      f"{n_tiles} tiles scaled to the whole frame; single-threaded NumPy FP64"}
+def oracle_table(log):
+    """The oracle per view on the parity workloads, at one process and at one process
+    per host core: 1k Gaussians at 128x128 (forward only, every tile), 100k at 1280x720,
+    3M at 1920x1080 and one 1920x1080 view of the 1M-Gaussian multi-view scene (fwd+bwd,
+    sampled tiles)."""
+    import scenes
+    P = oracle_procs()
+    rows = []
+    for name, fwd_only in (("small", True), ("single720", False), ("full1080", False),
+                           ("multiview", False)):
+        sc, cams = scenes.workload(name)
+        cam = cams[0]
+        if name == "multiview":
+            cam = next(c for c in cams if c.width == 1920)
+        row = {"workload": name, "gaussians": sc.n, "resolution": f"{cam.width}x{cam.height}",
+               "pass": "fwd" if fwd_only else "fwd+bwd", "processes": P}
+        for procs in sorted({1, P}):
+            t = oracle_view_seconds(sc, cam, procs, 48 if procs == 1 else 16, fwd_only)
+            row[f"view_s_{procs}"] = round(t["view_s"], 3)
+            row[f"tiles_sampled_{procs}"] = t["tiles_sampled"]
+            log(f"[oracle] {name} {procs} process(es): {t['view_s']:.2f} s per view")
+        rows.append(row)
+    print(json.dumps({"oracle_seconds_per_view": rows, "host_cores": os.cpu_count()}), flush=True)
 
 
 if __name__ == "__main__":
