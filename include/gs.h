@@ -66,7 +66,8 @@ enum {
   GS_ERR_CAPACITY = -2,    /* device status: more instances than capacity */
   GS_ERR_HIP = -3,         /* a HIP launch failed */
   GS_ERR_UNSUPPORTED = -4, /* size beyond a documented limit */
-  GS_ERR_SORT = -5         /* device status: sort look-back did not complete */
+  GS_ERR_SORT = -5,        /* device status: sort look-back did not complete */
+  GS_ERR_SCRATCH = -6      /* the call needs more than the library's static scratch */
 };
 
 /* bits of the device status word */
@@ -206,6 +207,22 @@ size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total, const gs
 int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
             uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
             size_t workspace_bytes, gs_stream_t stream);
+
+/* gs_sort without a workspace argument, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): identical
+ * arguments, results and errors, but the scratch memory is the library's own static
+ * device array of GS_SORT_SCRATCH_BYTES, one per GPU, held until the process ends. The
+ * call allocates and frees nothing. Limit: gs_sort_workspace_bytes(inst->capacity,
+ * n_tiles_total, cfg) must not exceed GS_SORT_SCRATCH_BYTES (else GS_ERR_SCRATCH and
+ * nothing is enqueued); 16 MiB covers, e.g., 20M instances with two 8-bit tile passes.
+ * The array belongs to the device current at the call (the stream must be on it); the
+ * first call on a device looks up its address there (hipGetSymbolAddress: make that
+ * first call outside graph capture). Every call clears what it needs inside the array,
+ * but all calls on one GPU share it: calls that overlap in time on one GPU (on
+ * different streams) race and give wrong results. */
+#define GS_SORT_SCRATCH_BYTES ((size_t)16 << 20)
+int gs_sort_noalloc(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
+                    uint32_t* tile_ranges, uint32_t* tile_order, gs_stream_t stream);
 
 /* Device address of the sorted global tile id of every instance after gs_sort
  * (uint32 [M], inside inst->keys or inst->keys_alt), or NULL on bad arguments. */

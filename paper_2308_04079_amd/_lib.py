@@ -20,7 +20,8 @@ MAX_INSTANCES = (1 << 30) - 1
 STATUS_CAPACITY = 1
 STATUS_SORT = 2
 
-OK, ERR_ARG, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED, ERR_SORT = 0, -1, -2, -3, -4, -5
+OK, ERR_ARG, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED, ERR_SORT, ERR_SCRATCH = 0, -1, -2, -3, -4, -5, -6
+SORT_SCRATCH_BYTES = 16 << 20
 
 c_float_p = ctypes.c_void_p
 
@@ -87,6 +88,8 @@ EXPORTS = {
     "gs_sort": (ctypes.c_int, [P(GsInstances), ctypes.c_int64, P(GsConfig), ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                ctypes.c_void_p]),
+    "gs_sort_noalloc": (ctypes.c_int, [P(GsInstances), ctypes.c_int64, P(GsConfig),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gs_render_fwd": (ctypes.c_int, [P(GsProjected), P(GsInstances), ctypes.c_void_p,
                                      ctypes.c_void_p, P(GsCamera), ctypes.c_int32, P(GsConfig),
                                      ctypes.c_void_p,

@@ -142,6 +142,7 @@ extern "C" const char* gs_status_string(int code) {
     case GS_ERR_HIP: return "HIP launch failed";
     case GS_ERR_UNSUPPORTED: return "size beyond a documented limit";
     case GS_ERR_SORT: return "sort look-back did not complete";
+    case GS_ERR_SCRATCH: return "needs more than the library's static scratch";
     default: return "unknown status";
   }
 }

@@ -15,6 +15,7 @@
 // look-back over the blocks before it, and scatters the pairs, staged through LDS so
 // the writes of a digit run are contiguous.
 #include <algorithm>
+#include <mutex>
 
 #include "gs_internal.h"
 
@@ -462,26 +463,17 @@ extern "C" const uint32_t* gs_sorted_tile_ids(const gs_instances* inst, int64_t 
       .sorted_tiles;
 }
 
-extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
-                       uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
-                       size_t workspace_bytes, gs_stream_t stream) {
-  if (!inst || !cfg || !tile_ranges || !workspace || n_tiles_total < 1) return GS_ERR_ARG;
-  int rc = check_config(cfg);
-  if (rc != GS_OK) return rc;
-  if (!inst->keys || !inst->vals || !inst->keys_alt || !inst->vals_alt || !inst->count ||
-      !inst->status || inst->capacity < 0)
-    return GS_ERR_ARG;
-  if (inst->capacity > GS_MAX_INSTANCES) return GS_ERR_UNSUPPORTED;
-  if (n_tiles_total >= ((int64_t)1 << 31)) return GS_ERR_UNSUPPORTED;
-  if (workspace_bytes < gs_sort_workspace_bytes(inst->capacity, n_tiles_total, cfg)) return GS_ERR_ARG;
+// Enqueue the sort into the given workspace (the caller's, or the static scratch).
+static int sort_impl(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
+                     uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
+                     size_t workspace_bytes, hipStream_t s) {
   const int bits = tile_key_bits(n_tiles_total);
   const int passes = radix_passes(bits, cfg->sort_digit_bits);
   if (passes > kMaxPasses) return GS_ERR_UNSUPPORTED;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const InstanceBufs b = instance_bufs(inst, passes);
   const int64_t cap = inst->capacity;
-  rc = radix_sort(b.tiles, 0, inst->count, cap, bits, cfg->sort_digit_bits, workspace,
-                  workspace_bytes, inst->status, s);
+  int rc = radix_sort(b.tiles, 0, inst->count, cap, bits, cfg->sort_digit_bits, workspace,
+                      workspace_bytes, inst->status, s);
   if (rc != GS_OK) return rc;
   sort_ranges<<<dim3((unsigned)((n_tiles_total + 255) / 256)), 256, 0, s>>>(
       b.sorted_tiles, inst->count, cap, n_tiles_total, tile_ranges);
@@ -494,4 +486,72 @@ extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs
                                                                (int)nb, tile_order);
   }
   return launch_status();
+}
+
+static int check_sort_args(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
+                           const uint32_t* tile_ranges) {
+  if (!inst || !cfg || !tile_ranges || n_tiles_total < 1) return GS_ERR_ARG;
+  const int rc = check_config(cfg);
+  if (rc != GS_OK) return rc;
+  if (!inst->keys || !inst->vals || !inst->keys_alt || !inst->vals_alt || !inst->count ||
+      !inst->status || inst->capacity < 0)
+    return GS_ERR_ARG;
+  if (inst->capacity > GS_MAX_INSTANCES) return GS_ERR_UNSUPPORTED;
+  if (n_tiles_total >= ((int64_t)1 << 31)) return GS_ERR_UNSUPPORTED;
+  return GS_OK;
+}
+
+extern "C" int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,
+                       uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
+                       size_t workspace_bytes, gs_stream_t stream) {
+  int rc = check_sort_args(inst, n_tiles_total, cfg, tile_ranges);
+  if (rc != GS_OK) return rc;
+  if (!workspace) return GS_ERR_ARG;
+  if (workspace_bytes < gs_sort_workspace_bytes(inst->capacity, n_tiles_total, cfg)) return GS_ERR_ARG;
+  return sort_impl(inst, n_tiles_total, cfg, tile_ranges, tile_order, workspace, workspace_bytes,
+                   reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// gs_sort_noalloc: the same sort with the library's static scratch as workspace
+// ---------------------------------------------------------------------------
+
+// The static scratch: each GPU the library runs on holds its own copy. In host code
+// this name is only a handle for hipGetSymbolAddress, never a device address.
+static __device__ __align__(256) unsigned char scratch[GS_SORT_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+// Device address of the current device's copy of the scratch, looked up on the first
+// call on that device.
+static int scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
+  if (dev < 0 || dev >= kMaxScratchDevices) return GS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
+extern "C" int gs_sort_noalloc(const gs_instances* inst, int64_t n_tiles_total,
+                               const gs_config* cfg, uint32_t* tile_ranges, uint32_t* tile_order,
+                               gs_stream_t stream) {
+  int rc = check_sort_args(inst, n_tiles_total, cfg, tile_ranges);
+  if (rc != GS_OK) return rc;
+  if (gs_sort_workspace_bytes(inst->capacity, n_tiles_total, cfg) > GS_SORT_SCRATCH_BYTES)
+    return GS_ERR_SCRATCH;
+  void* ws = nullptr;
+  rc = scratch_for_current_device(&ws);
+  if (rc != GS_OK) return rc;
+  return sort_impl(inst, n_tiles_total, cfg, tile_ranges, tile_order, ws, GS_SORT_SCRATCH_BYTES,
+                   reinterpret_cast<hipStream_t>(stream));
 }

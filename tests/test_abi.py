@@ -93,6 +93,16 @@ def test_host_argument_checks_return_before_any_launch(L):
     huge = L.make_cameras([scenes.pinhole_camera(40000, 8)])
     assert lib.gs_render_fwd(ctypes.byref(proj), ctypes.byref(inst), 1, None, huge, 1, ctypes.byref(cfg), 1, 1, 1, 1, None) == L.ERR_UNSUPPORTED
     assert lib.gs_sort(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, None, 0, None) == L.ERR_ARG
+    # the static-scratch sort: the same argument checks, then its size limit, all before
+    # any device call (the pointers below are never dereferenced)
+    assert lib.gs_sort_noalloc(ctypes.byref(inst), 10, ctypes.byref(cfg), None, None, None) == L.ERR_ARG
+    fake = L.GsInstances(16, 16, 16, 16, 1 << 27, 16, 16)
+    assert lib.gs_sort_workspace_bytes(1 << 27, 8160, ctypes.byref(cfg)) > L.SORT_SCRATCH_BYTES
+    assert lib.gs_sort_noalloc(ctypes.byref(fake), 8160, ctypes.byref(cfg), 16, None, None) == L.ERR_SCRATCH
+    fake.capacity = 1 << 30
+    assert lib.gs_sort_noalloc(ctypes.byref(fake), 8160, ctypes.byref(cfg), 16, None, None) == L.ERR_UNSUPPORTED
+    assert lib.gs_sort_noalloc(ctypes.byref(fake), 8160, ctypes.byref(bad), 16, None, None) == L.ERR_ARG
+    assert lib.gs_status_string(L.ERR_SCRATCH) == b"needs more than the library's static scratch"
     # two 8-bit passes over the 13 tile-id bits of one 1080p view
     assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) > (1 << 20) // 4096 * 2 * 1024
     assert lib.gs_sort_key_bits(8160) == 13 and lib.gs_sort_key_bits(1) == 0
