@@ -30,19 +30,27 @@ struct Eval {
   float di, dj, e0, e1, m, G, alpha;
 };
 
+// exp(-m/2) = 2^(m * (-log2(e) / 2)): -0.5 times the FP32 log2(e) is exact, and so is
+// the halving of m, so this one product equals the rounded (-m/2) * log2(e) of the
+// two-multiply form bit for bit.
+constexpr float kNegHalfLog2e = -0.5f * 1.44269502f;
+
+
 // The one alpha evaluation used by both passes: identical instruction sequences
 // (the library is built with -ffp-contract=off), hence identical decisions. The
 // pixel's offset D from the corner centre is exact (integers), and its whitened offset
 // from the mean is e = L^-1 D + c.
 __device__ __forceinline__ void eval_alpha(const float4& geo, const float4& shape, float fpx,
-                                           float fpy, const Rules& r, Eval& e) {
+                                           float fpy, float amax, Eval& e) {
   e.di = fpx - geo.x;
   e.dj = fpy - geo.y;
   e.e0 = fmaf(shape.x, e.di, geo.z);
   e.e1 = fmaf(shape.y, e.di, fmaf(shape.z, e.dj, geo.w));
   e.m = fmaf(e.e0, e.e0, e.e1 * e.e1);
-  e.G = __expf(-0.5f * e.m);
-  e.alpha = fminf(r.alpha_max, shape.w * e.G);
+  e.G = __builtin_amdgcn_exp2f(e.m * kNegHalfLog2e);
+  // min(amax, o G) as one median-of-three (o G >= 0: opacity and G are in [0, 1]);
+  // fminf would also re-canonicalise amax at every evaluation
+  e.alpha = __builtin_amdgcn_fmed3f(shape.w * e.G, 0.0f, amax);
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -330,6 +338,7 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   uint32_t start, end;
   tile_range(ranges, w.tile, tv.n_inst, start, end);
   const float fpx = (float)w.px + 0.5f, fpy = (float)w.py + 0.5f;
+  const float amax = rules.alpha_max;
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int32_t last = -1;
   // 1 while the pixel still blends, 0 once it stopped (or lies outside the image): a
@@ -360,7 +369,7 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
         const float4 shape = s.shape[slot];
         const float4 col = s.col[slot];
         Eval e;
-        eval_alpha(geo, shape, fpx, fpy, rules, e);
+        eval_alpha(geo, shape, fpx, fpy, amax, e);
         // branch-free: every lane evaluates. a is alpha where the Gaussian is taken
         // (inside the extent, alpha >= alpha_min > 0, pixel live), else 0; an untaken
         // entry then leaves T * (1 - 0) = T >= T_min, so only a taken one can stop
@@ -563,6 +572,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   uint32_t start, end;
   tile_range(ranges, w.tile, tv.n_inst, start, end);
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const float amax = rules.alpha_max;
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
   int32_t last = -1;
   if (inside) {
@@ -597,7 +607,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       for (int k = 0; k < cnt; ++k) {
         const int32_t pos = (int32_t)__float_as_uint(s.aux[k].z);
         Eval e;
-        eval_alpha(s.geo[k], s.shape[k], fpx, fpy, rules, e);
+        eval_alpha(s.geo[k], s.shape[k], fpx, fpy, amax, e);
         n_blended += ((pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min)) ? 1 : 0;
       }
       __builtin_amdgcn_wave_barrier();
@@ -618,7 +628,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       const float4 aux = s.aux[k];
       const int32_t pos = (int32_t)__float_as_uint(aux.z);
       Eval e;
-      eval_alpha(geo, shape, fpx, fpy, rules, e);
+      eval_alpha(geo, shape, fpx, fpy, amax, e);
       // branch-free: non-contributing lanes add zeros and keep their state
       const bool contrib = (pos <= last) && (e.m <= rules.ext2) && (e.alpha >= rules.alpha_min);
       bool grad_on = contrib;
