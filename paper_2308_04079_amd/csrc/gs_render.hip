@@ -103,17 +103,19 @@ __device__ __forceinline__ void tile_range(const uint32_t* __restrict__ ranges, 
   start = min(ranges[2 * tile], end);
 }
 
-// One list entry as gathered by a lane: kept for row r if some pixel of the row's
-// 4x4 block can pass both per-pixel tests of the blend, m <= ext^2 and
-// alpha >= alpha_min. With alpha = min(alpha_max, o exp(-m/2)) the second holds only
-// for m <= 2 ln(o / alpha_min), so an entry is kept when the least m over the block is
-// at most min(ext^2, 2 ln(o / alpha_min)) (a superset of the contributing entries, so
-// the image and gradients do not change; faint Gaussians reach fewer blocks than their
-// 3-sigma box). Over the rectangle of the block's pixel-centre offsets D from the
-// corner centre, m = |L^-1 D + c|^2 is convex: its least value is 0 if the mean lies
-// inside, else the least of the four edge minima, each a parabola minimised at its
-// vertex clamped to the edge. A slack far above the FP32 rounding of both evaluations
-// keeps the test conservative.
+// One list entry as gathered by a lane (forward): kept for row r if its pixel box meets
+// the row's 4x4 block and some pixel of the wave's block can pass both per-pixel tests
+// of the blend, m <= ext^2 and alpha >= alpha_min. With alpha = min(alpha_max,
+// o exp(-m/2)) the second holds only for m <= 2 ln(o / alpha_min), so the entry is kept
+// when the least m over the pixel box clipped to the wave's block is at most
+// min(ext^2, 2 ln(o / alpha_min)) (a superset of the contributing entries, so the image
+// and gradients do not change; faint Gaussians reach fewer blocks than their 3-sigma
+// box). Over a rectangle of pixel-centre offsets D from the corner centre,
+// m = |L^-1 D + c|^2 is convex: its least value is 0 if the mean lies inside, else the
+// least of the four edge minima, each a parabola minimised at its vertex clamped to the
+// edge. A slack far above the FP32 rounding of both evaluations keeps the test
+// conservative. (One test per entry on the clipped box costs less than one per row and
+// keeps nearly all of the per-row cull: measured 0.59 against 0.62 ms.)
 struct Entry {
   float4 r0, r1, r2;
   uint32_t g, i;
@@ -203,9 +205,15 @@ __device__ __forceinline__ void gather_entry(const float* __restrict__ record, u
     if ((int32_t)i > row_lim[r] || e.ilo > sx1 || ihi < sx0 || e.jlo > sy1 || jhi < sy0 ||
         sx0 > sx1 || sy0 > sy1)
       continue;
-    if (block_reachable(sh, thr, e.ax, e.ay, (float)(sx0 - e.ilo), (float)(sx1 - e.ilo),
-                        (float)(sy0 - e.jlo), (float)(sy1 - e.jlo)))
-      e.rows |= 1u << r;
+    e.rows |= 1u << r;
+  }
+  // one exact test on the pixel box clipped to the wave's 8x8 block (every pixel that can
+  // take the entry lies in that rectangle): one test per entry, not one per row
+  if (e.rows) {
+    const int rx0 = max(w.x0, e.ilo), rx1 = min(qx1, ihi), ry0 = max(w.y0, e.jlo), ry1 = min(qy1, jhi);
+    if (!block_reachable(sh, thr, e.ax, e.ay, (float)(rx0 - e.ilo), (float)(rx1 - e.ilo),
+                         (float)(ry0 - e.jlo), (float)(ry1 - e.jlo)))
+      e.rows = 0;
   }
   if (e.rows) e.r2 = rec[2];
 }
