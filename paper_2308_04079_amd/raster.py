@@ -158,7 +158,7 @@ class Rasterizer:
             pix.append(pix[-1] + int(c.width) * int(c.height))
 
         depth_key = torch.empty(max(1, V * n), dtype=torch.int32, device=dev)
-        tiles_touched = torch.zeros(max(1, V * n), dtype=torch.int32, device=dev)
+        tiles_touched = torch.empty(max(1, V * n), dtype=torch.int32, device=dev)  # gs_project writes all
         record = torch.empty(max(1, V * n) * _lib.RECORD_FLOATS, dtype=torch.float32, device=dev)
         pr = params.c_struct()
         proj = _lib.GsProjected(_lib.ptr(depth_key), _lib.ptr(tiles_touched), _lib.ptr(record))
