@@ -443,27 +443,38 @@ __device__ __forceinline__ int row_max_int(int x) {
 // copy of them (9 -> 5 -> 3 -> 2 -> 1 registers). The partners l ^ 15 and l ^ 7 differ
 // in all low bits, so they come first (split on bit 3, then bit 2), then l ^ 2 and
 // l ^ 1. Row lane l then holds its row's total of value reduce_index(l) when bit l of
-// kReduceLanes is set.
+// kReduceLanes is set. A value without a partner at a step (a4, then x2, then y1) is
+// added to its partner lane's copy on both lanes, with no selects: on the lanes that
+// should hold nothing in that slot the copy lands in a slot past the ninth value, and
+// every later partner shares the bits already split on, so it never reaches a kept lane
+// (the kept lanes add the same operands as with an explicit zero).
 constexpr uint32_t kReduceLanes = 0x1737u;  // row lanes 0, 1, 2, 4, 5, 8, 9, 10, 12
 __device__ __forceinline__ int reduce_index(uint32_t l) {
   return 5 * ((l >> 3) & 1) + 3 * ((l >> 2) & 1) + 2 * ((l >> 1) & 1) + (l & 1);
 }
 
-__device__ __forceinline__ float row_reduce9_scatter(float a0, float a1, float a2, float a3,
-                                                     float a4, float a5, float a6, float a7,
+// Value v of the butterfly is grad2d component (kSlotOfValue >> 4 v) & 15: the values
+// are, in order, d_r, d_mx, d_my, d_w00, d_w11, d_g, d_o, d_b, d_w10, so that the first
+// pair (values 0 and 5) is the red and green gradient, both the step's blend weight
+// times a per-pixel constant: the lane's kept and sent constants of that pair are
+// chosen once per pixel (k0 = w g_keep, s0 = w g_send), not selected at every step.
+constexpr uint64_t kSlotOfValue = 0x385742106ull;
+
+__device__ __forceinline__ float row_reduce9_scatter(float k0, float s0, float a1, float a2,
+                                                     float a3, float a4, float a6, float a7,
                                                      float a8) {
   const uint32_t l = __lane_id() & 15;
   const bool h3 = l & 8, h2 = l & 4, h1 = l & 2, h0 = l & 1;
-  const float x0 = (h3 ? a5 : a0) + lane_xor<15>(h3 ? a0 : a5);
+  const float x0 = k0 + lane_xor<15>(s0);
   const float x1 = (h3 ? a6 : a1) + lane_xor<15>(h3 ? a1 : a6);
   const float x2 = (h3 ? a7 : a2) + lane_xor<15>(h3 ? a2 : a7);
   const float x3 = (h3 ? a8 : a3) + lane_xor<15>(h3 ? a3 : a8);
-  const float x4 = (h3 ? 0.0f : a4) + lane_xor<15>(h3 ? a4 : 0.0f);
+  const float x4 = a4 + lane_xor<15>(a4);
   const float y0 = (h2 ? x3 : x0) + lane_xor<7>(h2 ? x0 : x3);
   const float y1 = (h2 ? x4 : x1) + lane_xor<7>(h2 ? x1 : x4);
-  const float y2 = (h2 ? 0.0f : x2) + lane_xor<7>(h2 ? x2 : 0.0f);
+  const float y2 = x2 + lane_xor<7>(x2);
   const float z0 = (h1 ? y2 : y0) + lane_xor<2>(h1 ? y0 : y2);
-  const float z1 = (h1 ? 0.0f : y1) + lane_xor<2>(h1 ? y1 : 0.0f);
+  const float z1 = y1 + lane_xor<2>(y1);
   return (h0 ? z1 : z0) + lane_xor<1>(h0 ? z0 : z1);
 }
 
@@ -602,7 +613,11 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   const int32_t wave_last = min(wave_max_int(last), (int32_t)end - 1);
   if (wave_last < (int32_t)start) return;  // no pixel of this wave blended anything
   const bool atomic_lane = lane < kRowLanes && ((kReduceLanes >> lane) & 1u);
-  const int atomic_slot = reduce_index((uint32_t)lane);
+  const int atomic_slot = (int)((kSlotOfValue >> (4 * reduce_index((uint32_t)lane))) & 15u);
+  // the red / green pair of the butterfly's first step: the colour constant this lane
+  // keeps and the one it sends to its partner l ^ 15
+  const bool upper = lane & 8;
+  const float g_keep = upper ? g1 : g0, g_send = upper ? g0 : g1;
   // limited-gradient ablation: count the pixel's blended Gaussians first, so the
   // back-to-front walk knows each one's front-to-back rank
   int n_blended = 0, from_back = 0;
@@ -648,7 +663,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       T = T * inv;  // transmittance in front of this Gaussian
       const float wgt = contrib ? T * e.alpha : 0.0f;
       const float gwgt = grad_on ? wgt : 0.0f;
-      const float d_r = gwgt * g0, d_g = gwgt * g1, d_b = gwgt * g2;
+      const float d_b = gwgt * g2;
       const float gc = fmaf(g2, col.z, fmaf(g1, col.y, g0 * col.x));
       float dalpha = fmaf(T, gc, -S * inv);
       S = fmaf(wgt, gc, S);
@@ -664,7 +679,8 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       const float dx = e.di - aux.x, dy = e.dj - aux.y;
       const float d_w00 = t0 * dx, d_w10 = t1 * dx, d_w11 = t1 * dy;
       if (__ballot(grad_on) != 0ull) {
-        float tot = row_reduce9_scatter(d_mx, d_my, d_w00, d_w10, d_w11, d_o, d_r, d_g, d_b);
+        float tot = row_reduce9_scatter(gwgt * g_keep, gwgt * g_send, d_mx, d_my, d_w00, d_w11,
+                                        d_o, d_b, d_w10);
         tot += __shfl_xor(tot, 16, kWave);
         tot += __shfl_xor(tot, 32, kWave);
         const uint32_t rec = __float_as_uint(col.w);
