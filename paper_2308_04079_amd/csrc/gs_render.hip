@@ -349,14 +349,13 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   const float amax = rules.alpha_max;
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int32_t last = -1;
-  // 1 while the pixel still blends, 0 once it stopped (or lies outside the image): a
-  // float, so that every decision below is a compare feeding one select, with no
-  // combining of lane masks
-  float live = w.inside ? 1.0f : 0.0f;
+  // the smallest alpha the pixel still takes: alpha_min while it blends, +inf once it
+  // stopped (or when it lies outside the image), so that one compare decides both
+  float amin = w.inside ? rules.alpha_min : INFINITY;
   Ahead<R> ahead;
   load_ahead<BATCH>(vals, start, (int64_t)end - 1, ahead);
   for (uint32_t base = start; base < end; base += BATCH) {
-    const uint64_t lv = __ballot(live > 0.0f);
+    const uint64_t lv = __ballot(amin < INFINITY);
     if (lv == 0ull) break;
     int32_t row_lim[kRows];
 #pragma unroll
@@ -380,22 +379,23 @@ render_fwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
         eval_alpha(geo, shape, fpx, fpy, amax, e);
         // branch-free: every lane evaluates. a is alpha where the Gaussian is taken
         // (inside the extent, alpha >= alpha_min > 0, pixel live), else 0; an untaken
-        // entry then leaves T * (1 - 0) = T >= T_min, so only a taken one can stop
-        float a = (e.m <= rules.ext2) ? e.alpha : 0.0f;
-        a = (a >= rules.alpha_min) ? a : 0.0f;
-        a *= live;
+        // entry then leaves T * (1 - 0) = T >= T_min, so only a taken one can stop.
+        // The two tests form one lane mask and one select; the blended mask (taken and
+        // not stopping) selects the weight and the last contributor.
+        const bool take = (e.m <= rules.ext2) & (e.alpha >= amin);
+        const float a = take ? e.alpha : 0.0f;
         const float Tn = T * (1.0f - a);
         const bool stop = Tn < rules.T_min;
-        const float ab = stop ? 0.0f : a;   // alpha of a blended entry, else 0
-        const float wgt = T * ab;
+        const bool blend = take & !stop;
+        const float wgt = T * (blend ? a : 0.0f);
         C0 = fmaf(wgt, col.x, C0);
         C1 = fmaf(wgt, col.y, C1);
         C2 = fmaf(wgt, col.z, C2);
         T = stop ? T : Tn;
-        last = (ab > 0.0f) ? (int32_t)__float_as_uint(col.w) : last;
-        live = stop ? 0.0f : live;
+        last = blend ? (int32_t)__float_as_uint(col.w) : last;
+        amin = stop ? INFINITY : amin;
       }
-      all_done = __ballot(live > 0.0f) == 0ull;
+      all_done = __ballot(amin < INFINITY) == 0ull;
     }
     __builtin_amdgcn_wave_barrier();
   }
