@@ -659,10 +659,16 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
         grad_on = contrib && (n_blended - 1 - from_back) < rules.grad_limit;
         from_back += contrib ? 1 : 0;
       }
-      const float inv = contrib ? __builtin_amdgcn_rcpf(1.0f - e.alpha) : 1.0f;
+      // alpha of a contributing entry, else 0: then 1 / (1 - a) is exactly 1 (the hardware
+      // reciprocal is exact at powers of two) and the weight 0, with one select
+      const float a = contrib ? e.alpha : 0.0f;
+      const float inv = __builtin_amdgcn_rcpf(1.0f - a);
       T = T * inv;  // transmittance in front of this Gaussian
-      const float wgt = contrib ? T * e.alpha : 0.0f;
-      const float gwgt = grad_on ? wgt : 0.0f;
+      const float wgt = T * a;
+      // wgt is already 0 where the entry does not contribute; only the limited-gradient
+      // ablation drops contributing entries from the gradient
+      float gwgt = wgt;
+      if constexpr (LIMIT) gwgt = grad_on ? wgt : 0.0f;
       const float d_b = gwgt * g2;
       const float gc = fmaf(g2, col.z, fmaf(g1, col.y, g0 * col.x));
       float dalpha = fmaf(T, gc, -S * inv);
@@ -683,8 +689,9 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
                                         d_o, d_b, d_w10);
         tot += __shfl_xor(tot, 16, kWave);
         tot += __shfl_xor(tot, 32, kWave);
+        // staged entries hold record indices below n_records (gather_block_entry)
         const uint32_t rec = __float_as_uint(col.w);
-        if (atomic_lane && tot != 0.0f && rec < tv.n_records)
+        if (atomic_lane && tot != 0.0f)
           atomicAdd(grad2d + (size_t)rec * GS_GRAD2D_FLOATS + atomic_slot, tot);
       }
     }
