@@ -26,8 +26,8 @@
  *   and returns; the sequence is capturable into a HIP graph.
  * - Errors: the return value reports argument errors found on the host
  *   (GS_ERR_ARG, GS_ERR_UNSUPPORTED) and launch failures (GS_ERR_HIP). Errors that
- *   can only be known on the device (too many instances for the capacity, a sort
- *   look-back that did not complete) are OR-ed into the device status word
+ *   can only be known on the device (too many instances for the capacity) are OR-ed
+ *   into the device status word
  *   gs_instances.status; read it after the stream completes (gs_read_status).
  *   On a device-side error the outputs are unspecified but every kernel stays
  *   inside the caller's buffers.
@@ -57,8 +57,8 @@ typedef struct ihipStream_t* gs_stream_t; /* identical to hipStream_t */
 #define GS_MAX_DIM 32767       /* largest image width or height */
 #define GS_RECORD_FLOATS 12    /* floats per projected Gaussian record */
 #define GS_GRAD2D_FLOATS 9     /* floats per screen-space gradient record */
-#define GS_MAX_INSTANCES (((int64_t)1 << 30) - 1) /* largest instance capacity: the sort's
-                                                     look-back packs prefix counts in 30 bits */
+#define GS_MAX_INSTANCES (((int64_t)1 << 30) - 1) /* largest instance capacity (instance
+                                                     positions are int32 in last_idx) */
 
 enum {
   GS_OK = 0,
@@ -66,7 +66,8 @@ enum {
   GS_ERR_CAPACITY = -2,    /* device status: more instances than capacity */
   GS_ERR_HIP = -3,         /* a HIP launch failed */
   GS_ERR_UNSUPPORTED = -4, /* size beyond a documented limit */
-  GS_ERR_SORT = -5,        /* device status: sort look-back did not complete */
+  GS_ERR_SORT = -5,        /* device status GS_STATUS_SORT (reserved: the current sort
+                              has no device-side failure and never raises it) */
   GS_ERR_SCRATCH = -6      /* the call needs more than the library's static scratch */
 };
 
@@ -198,8 +199,8 @@ int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams, int32_t n
 size_t gs_sort_workspace_bytes(int64_t capacity, int64_t n_tiles_total, const gs_config* cfg);
 
 /* Sort (Alg. 2 SortByKeys + IdentifyTileRanges; App. C): stable LSD radix sort of
- * the M = min(*count, capacity) instances of gs_bin by global tile id (onesweep:
- * one histogram pass, then one pass per digit with decoupled look-back), which
+ * the M = min(*count, capacity) instances of gs_bin by global tile id (per digit a
+ * counting pass, a scan of the per-block counts, and a scatter pass), which
  * completes the (tile, depth, index) order, then per global tile the range
  * [start, end) of its instances, written to tile_ranges[t][2] (uint32). If tile_order (device, [n_tiles_total])
  * is not NULL it receives a permutation of the tile ids, longest list first
@@ -214,11 +215,11 @@ int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cf
  * device array of GS_SORT_SCRATCH_BYTES, one per GPU, held until the process ends. The
  * call allocates and frees nothing. Limit: gs_sort_workspace_bytes(inst->capacity,
  * n_tiles_total, cfg) must not exceed GS_SORT_SCRATCH_BYTES (else GS_ERR_SCRATCH and
- * nothing is enqueued); 16 MiB covers, e.g., 20M instances with two 8-bit tile passes.
+ * nothing is enqueued); 16 MiB covers about 67M instances (1 KiB per 4096).
  * The array belongs to the device current at the call (the stream must be on it); the
  * first call on a device looks up its address there (hipGetSymbolAddress: make that
- * first call outside graph capture). Every call clears what it needs inside the array,
- * but all calls on one GPU share it: calls that overlap in time on one GPU (on
+ * first call outside graph capture). No part of the array needs to start at zero
+ * (every call writes what it reads), but all calls on one GPU share it: calls that overlap in time on one GPU (on
  * different streams) race and give wrong results. */
 #define GS_SORT_SCRATCH_BYTES ((size_t)16 << 20)
 int gs_sort_noalloc(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cfg,

@@ -449,8 +449,7 @@ extern "C" int gs_bin(const gs_projected* proj, int64_t n, const gs_camera* cams
         b.depth.vals[0]);
   // 2. by depth (stable: ties keep index order)
   const int64_t max_vis = std::min(total, cap);
-  rc = radix_sort(b.depth, 0, w.misc + 1, max_vis, kDepthKeyBits, db, w.radix, w.radix_bytes,
-                  inst->status, s);
+  rc = radix_sort(b.depth, 0, w.misc + 1, max_vis, kDepthKeyBits, db, w.radix, w.radix_bytes, s);
   if (rc != GS_OK) return rc;
   const uint32_t* sorted = b.depth.vals[radix_passes(kDepthKeyBits, db) & 1];
   // 3. tile rectangles in depth order -> instance offsets, count and capacity check.

@@ -29,8 +29,7 @@ size_t radix_workspace_bytes(int64_t max_items, int passes);
 // Sorts min(*count, max_items) pairs on their low key_bits bits, starting in set
 // `start`; the result is in set (start + passes) & 1. Enqueue only.
 int radix_sort(const RadixBufs& b, int start, const uint32_t* count, int64_t max_items,
-               int key_bits, int digit_bits, void* ws, size_t ws_bytes, uint32_t* status,
-               hipStream_t s);
+               int key_bits, int digit_bits, void* ws, size_t ws_bytes, hipStream_t s);
 int tile_key_bits(int64_t n_tiles_total);
 InstanceBufs instance_bufs(const gs_instances* inst, int tile_passes);
 constexpr int kDepthKeyBits = 31;   // depth > 0: the sign bit of its float word is 0

@@ -7,13 +7,14 @@
 // the instance pass moves 8 bytes per instance over the tile bits only instead of
 // 12 bytes over tile + depth bits.
 //
-// Each radix sort has the onesweep structure (Adinets and Merrill, 2022): one
-// histogram pass over the keys computes the digit counts of every pass at once; then
-// each digit pass is a single launch in which a 256-thread block takes 4096 keys in
-// ticket order, ranks them in LDS (wave ballots find the lanes sharing a digit),
-// publishes its digit counts, resolves its global digit offsets by decoupled
-// look-back over the blocks before it, and scatters the pairs, staged through LDS so
-// the writes of a digit run are contiguous.
+// Each radix digit pass is reduce-then-scan, in three launches: a counting pass in
+// which every 256-thread block counts the digits of its 4096 keys (wave ballots find
+// the lanes sharing a digit), a scan with one workgroup per digit over the blocks'
+// counts, and a scatter pass in which every block ranks its keys again, reorders them
+// through LDS and writes each digit's run contiguously at its scanned offset. The keys
+// are read twice per pass, but no block waits on another: a single-launch pass with a
+// decoupled look-back (onesweep) chains every block to its predecessors through
+// device-scope loads, which on this chip cross the eight XCDs' L2s.
 #include <algorithm>
 #include <mutex>
 
@@ -24,25 +25,18 @@ namespace gs {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per block
-constexpr int kLookback = 8;                        // predecessors examined per step
+constexpr int kSortWaves = kSortBlock / kWave;
 constexpr int kMaxPasses = 8;
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagInc = 2u << 30;
-constexpr uint32_t kValueMask = (1u << 30) - 1;
-constexpr uint32_t kSpinLimit = 1u << 22;
-// The histogram pass adds its block counts into one of kHistCopies copies, chosen by
-// block index: consecutive blocks are dispatched to different XCDs (eight on MI355X),
-// so each copy collects the atomics of one XCD instead of all blocks contending for
-// the same words; the scan kernel sums the copies.
-constexpr int kHistCopies = 8;
-constexpr int kHistWords = kMaxPasses * 256;
+constexpr int kMaxRadix = 256;
+constexpr int kScanChunk = 16;                      // counts per scan load batch
 
+// Workspace: counts[RADIX][n_blocks], digit-major: the count pass writes how many keys
+// of block b have digit d, the scan replaces each with the block's exclusive offset
+// inside its digit; totals[RADIX] holds each digit's total. One set serves every pass.
 struct RadixWs {
-  uint32_t* hist;      // [kHistCopies][kMaxPasses][256] digit counts; copy 0 then holds
-                       // the exclusive scan of their sum
-  uint32_t* ticket;    // [kMaxPasses]
-  uint32_t* lookback;  // [passes][n_blocks][256]
-  int64_t n_blocks;
+  uint32_t* counts;
+  uint32_t* totals;
+  int64_t n_blocks;   // row length of counts: blocks of the largest item count
 };
 
 static int64_t radix_blocks(int64_t max_items) {
@@ -50,17 +44,16 @@ static int64_t radix_blocks(int64_t max_items) {
 }
 
 size_t radix_workspace_bytes(int64_t max_items, int passes) {
-  return (size_t)(kHistCopies * kHistWords + 64 + (int64_t)passes * radix_blocks(max_items) * 256) *
-         sizeof(uint32_t);
+  (void)passes;   // the passes run one after the other on the same counts
+  return (size_t)(kMaxRadix * radix_blocks(max_items) + kMaxRadix) * sizeof(uint32_t);
 }
 
 static RadixWs carve(void* ws, int64_t max_items) {
   RadixWs w;
   uint32_t* p = static_cast<uint32_t*>(ws);
   w.n_blocks = radix_blocks(max_items);
-  w.hist = p;
-  w.ticket = p + kHistCopies * kHistWords;
-  w.lookback = w.ticket + 64;
+  w.counts = p;
+  w.totals = p + (size_t)kMaxRadix * w.n_blocks;
   return w;
 }
 
@@ -68,112 +61,30 @@ __device__ __forceinline__ int64_t item_count(const uint32_t* count, int64_t max
   return min((int64_t)count[0], max_items);
 }
 
-__global__ void __launch_bounds__(256)
-radix_init(RadixWs w, int passes, const uint32_t* __restrict__ count, int64_t max_items) {
-  const int64_t M = item_count(count, max_items);
-  const int64_t nb = (M + kSortTile - 1) / kSortTile;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = t0; i < (int64_t)kHistCopies * kHistWords; i += stride) w.hist[i] = 0;
-  for (int64_t i = t0; i < 64; i += stride) w.ticket[i] = 0;
-  for (int p = 0; p < passes; ++p) {
-    uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
-    for (int64_t i = t0; i < nb * 256; i += stride) lb[i] = 0;
-  }
-}
-
-// Digit counts of every pass in one read of the keys: blocks take 4096-key tiles in
-// turn (sixteen loads in flight per thread), count in LDS, then add their counts to
-// their XCD's copy of the histogram.
-__global__ void __launch_bounds__(256)
-radix_histogram(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count,
-                int64_t max_items, int passes, int db, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t sh[kMaxPasses][256];
-  for (int i = threadIdx.x; i < kMaxPasses * 256; i += 256) (&sh[0][0])[i] = 0;
-  __syncthreads();
-  const int64_t M = item_count(count, max_items);
-  const uint32_t mask = (1u << db) - 1;
-  for (int64_t base = (int64_t)blockIdx.x * kSortTile; base < M;
-       base += (int64_t)gridDim.x * kSortTile) {
-    uint32_t k[kSortItems];
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-      const int64_t i = base + (int64_t)r * 256 + threadIdx.x;
-      k[r] = i < M ? keys[i] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-      if (base + (int64_t)r * 256 + threadIdx.x >= M) break;
-      for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k[r] >> (p * db)) & mask], 1u);
-    }
-  }
-  __syncthreads();
-  uint32_t* mine = hist + (size_t)(blockIdx.x % kHistCopies) * kHistWords;
-  for (int i = threadIdx.x; i < passes * 256; i += 256) {
-    const uint32_t c = (&sh[0][0])[i];
-    if (c) atomicAdd(&mine[i], c);
-  }
-}
-
-__global__ void __launch_bounds__(256)
-radix_scan_hist(uint32_t* __restrict__ hist, int passes) {
-  __shared__ uint32_t s[256];
-  const int t = threadIdx.x;
-  for (int p = 0; p < passes; ++p) {
-    uint32_t x = 0;
-#pragma unroll
-    for (int c = 0; c < kHistCopies; ++c) x += hist[c * kHistWords + p * 256 + t];
-    s[t] = x;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-      const uint32_t y = (t >= d) ? s[t - d] : 0u;
-      __syncthreads();
-      s[t] += y;
-      __syncthreads();
-    }
-    hist[p * 256 + t] = s[t] - x;
-    __syncthreads();
-  }
-}
-
+// The block's keys: wave w owns the contiguous run [b*4096 + w*1024, +1024), round r
+// lane l its item r*64 + l. Digits of missing items are RADIX (no digit).
 template <int DB>
-__global__ void __launch_bounds__(kSortBlock)
-radix_pass(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-           uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-           const uint32_t* __restrict__ count, int64_t max_items, int shift,
-           const uint32_t* __restrict__ digit_start, uint32_t* __restrict__ lookback,
-           uint32_t* __restrict__ ticket, uint32_t* __restrict__ status) {
+__device__ __forceinline__ void load_block_keys(const uint32_t* __restrict__ keys, int64_t b,
+                                                int64_t M, int shift, uint32_t* k, uint32_t* dig) {
   constexpr int RADIX = 1 << DB;
-  constexpr int WAVES = kSortBlock / kWave;
-  constexpr int WAVE_ITEMS = kSortTile / WAVES;
-  __shared__ uint32_t s_keys[kSortTile];
-  __shared__ uint32_t s_vals[kSortTile];
-  __shared__ uint32_t s_whist[WAVES][RADIX];
-  __shared__ uint32_t s_local_base[RADIX];
-  __shared__ uint32_t s_global_base[RADIX];
-  __shared__ uint32_t s_scan[WAVES];
-  __shared__ uint32_t s_tile;
-
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-  for (int i = tid; i < WAVES * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
-  __syncthreads();
-  const int64_t tile = s_tile;
-  const int64_t M = item_count(count, max_items);
-  if (tile * kSortTile >= M) return;  // uniform over the block
-
-  // load: wave w owns the contiguous run [tile*4096 + w*1024, +1024), round r lane l
-  const int64_t wbase = tile * kSortTile + (int64_t)wave * WAVE_ITEMS;
-  uint32_t k[kSortItems], val[kSortItems], dig[kSortItems], rank[kSortItems];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int64_t wbase = b * kSortTile + (int64_t)wave * (kSortTile / kSortWaves);
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = wbase + (int64_t)r * kWave + lane;
     const bool valid = i < M;
-    k[r] = valid ? keys_in[i] : 0u;
-    val[r] = valid ? vals_in[i] : 0u;
+    k[r] = valid ? keys[i] : 0u;
     dig[r] = valid ? ((k[r] >> shift) & (RADIX - 1)) : (uint32_t)RADIX;
   }
-  // rank in input order (round-major, then lane): stable
+}
+
+// Rank of every item among the wave's items of the same digit, in input order (round,
+// then lane): lanes sharing a digit are found with one ballot per digit bit. whist
+// (the wave's RADIX counters, zero on entry) ends holding the wave's digit counts.
+template <int DB>
+__device__ __forceinline__ void wave_rank(const uint32_t* dig, uint32_t* rank, uint32_t* whist) {
+  constexpr int RADIX = 1 << DB;
+  const int lane = threadIdx.x % kWave;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -187,85 +98,166 @@ radix_pass(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ va
     }
     uint32_t base = 0;
     if (valid) {
-      base = s_whist[wave][dig[r]];
+      base = whist[dig[r]];
       rank[r] = base + (uint32_t)__popcll(peers & lt_mask);
     }
     __builtin_amdgcn_wave_barrier();
     // the highest lane of each peer group writes the new count
-    if (valid && (peers >> lane) == 1ull) s_whist[wave][dig[r]] = base + (uint32_t)__popcll(peers);
+    if (valid && (peers >> lane) == 1ull) whist[dig[r]] = base + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
+}
 
-  // per digit: exclusive offsets of the waves, block total
-  uint32_t total = 0;
-  if (tid < RADIX) {
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      const uint32_t c = s_whist[w][tid];
-      s_whist[w][tid] = total;
-      total += c;
-    }
-  }
-  // decoupled look-back: thread d resolves digit d
-  if (tid < RADIX) {
-    uint32_t* mine = lookback + tile * RADIX + tid;
-    uint32_t excl = 0;
-    if (tile == 0) {
-      __hip_atomic_store(mine, kFlagInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(mine, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // windowed look-back: load kLookback predecessors at once (independent loads, one
-      // latency), add them nearest first up to the first inclusive prefix; on a
-      // not-yet-published entry, keep what was added and re-poll from that entry
-      int64_t t = tile - 1;
-      uint32_t spins = 0;
-      bool found = false;
-      while (!found) {
-        uint32_t wv[kLookback];
-#pragma unroll
-        for (int j = 0; j < kLookback; ++j)
-          wv[j] = (t - j >= 0) ? __hip_atomic_load(lookback + (t - j) * RADIX + tid, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT)
-                               : kFlagInc;  // before block 0: an empty inclusive prefix
-        int j = 0;
-        for (; j < kLookback; ++j) {
-          const uint32_t flag = wv[j] & ~kValueMask;
-          if (flag == 0) break;
-          excl += wv[j] & kValueMask;
-          if (flag == kFlagInc) {
-            found = true;
-            break;
-          }
-        }
-        if (found) break;
-        t -= j;
-        if (j < kLookback) {  // entry t not published yet
-          if (++spins > kSpinLimit) {  // never expected; bounded so the grid always drains
-            atomicOr(status, GS_STATUS_SORT);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      __hip_atomic_store(mine, kFlagInc | ((excl + total) & kValueMask), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_global_base[tid] = digit_start[tid] + excl;
-  }
-  // block-local exclusive scan of the digit totals: wave prefix sums, then the waves
-  uint32_t incl = (tid < RADIX) ? total : 0u;
+// Exclusive scan of one value per thread over the block (256 threads); *total receives
+// the sum. s holds kSortWaves words.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s, uint32_t* total) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  uint32_t incl = x;
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
     const uint32_t y = __shfl_up(incl, d, kWave);
     if (lane >= d) incl += y;
   }
-  if (lane == kWave - 1) s_scan[wave] = incl;
+  if (lane == kWave - 1) s[wave] = incl;
   __syncthreads();
-  uint32_t wbase_sum = 0;
+  uint32_t before = 0, all = 0;
 #pragma unroll
-  for (int w2 = 0; w2 < WAVES; ++w2) wbase_sum += (w2 < wave) ? s_scan[w2] : 0u;
-  if (tid < RADIX) s_local_base[tid] = wbase_sum + incl - total;
+  for (int w = 0; w < kSortWaves; ++w) {
+    before += (w < wave) ? s[w] : 0u;
+    all += s[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+// Counting pass: block b's digit counts to counts[d][b]. Blocks past the keys write
+// nothing (the scan and the scatter stop at the last block holding keys).
+template <int DB>
+__global__ void __launch_bounds__(kSortBlock)
+radix_count(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count,
+            int64_t max_items, int shift, int64_t n_blocks, uint32_t* __restrict__ counts) {
+  constexpr int RADIX = 1 << DB;
+  __shared__ uint32_t s_whist[kSortWaves][RADIX];
+  const int64_t b = blockIdx.x;
+  const int64_t M = item_count(count, max_items);
+  if (b * kSortTile >= M) return;   // uniform over the block
+  const int tid = threadIdx.x, wave = tid / kWave;
+  for (int i = tid; i < kSortWaves * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
+  uint32_t k[kSortItems], dig[kSortItems], rank[kSortItems];
+  load_block_keys<DB>(keys, b, M, shift, k, dig);
+  __syncthreads();
+  wave_rank<DB>(dig, rank, s_whist[wave]);
+  __syncthreads();
+  if (tid < RADIX) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) c += s_whist[w][tid];
+    counts[(int64_t)tid * n_blocks + b] = c;
+  }
+}
+
+// One workgroup per digit d: exclusive scan of counts[d][0..nb) in place (nb = blocks
+// holding keys), the digit's total to totals[d]. Thread t takes a contiguous run of
+// blocks and loads it kScanChunk counts at a time; the first chunk stays in registers.
+__global__ void __launch_bounds__(kSortBlock)
+radix_scan_counts(uint32_t* __restrict__ counts, const uint32_t* __restrict__ count,
+                  int64_t max_items, int64_t n_blocks, uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_scan[kSortWaves];
+  const int64_t M = item_count(count, max_items);
+  const int64_t nb = (M + kSortTile - 1) / kSortTile;
+  uint32_t* col = counts + (int64_t)blockIdx.x * n_blocks;
+  const int64_t per = (nb + kSortBlock - 1) / kSortBlock;
+  const int64_t lo = min(nb, (int64_t)threadIdx.x * per), hi = min(nb, lo + per);
+  uint32_t first[kScanChunk];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    first[j] = (lo + j < hi) ? col[lo + j] : 0u;
+    sum += first[j];
+  }
+  for (int64_t i0 = lo + kScanChunk; i0 < hi; i0 += kScanChunk) {
+    uint32_t x[kScanChunk];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) x[j] = (i0 + j < hi) ? col[i0 + j] : 0u;
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) sum += x[j];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan256(sum, s_scan, &total);
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    if (lo + j < hi) col[lo + j] = run;
+    run += first[j];
+  }
+  for (int64_t i0 = lo + kScanChunk; i0 < hi; i0 += kScanChunk) {
+    uint32_t x[kScanChunk];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) x[j] = (i0 + j < hi) ? col[i0 + j] : 0u;
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) {
+      if (i0 + j < hi) col[i0 + j] = run;
+      run += x[j];
+    }
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
+// Scatter pass: block b ranks its keys again as the counting pass did, places them in
+// block-sorted order through LDS, and writes each digit's run contiguously at
+// start[d] + offsets[d][b], start being the exclusive scan of the digit totals.
+template <int DB>
+__global__ void __launch_bounds__(kSortBlock)
+radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+              uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+              const uint32_t* __restrict__ count, int64_t max_items, int shift, int64_t n_blocks,
+              const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ totals) {
+  constexpr int RADIX = 1 << DB;
+  __shared__ uint32_t s_keys[kSortTile];
+  __shared__ uint32_t s_vals[kSortTile];
+  __shared__ uint32_t s_whist[kSortWaves][RADIX];
+  __shared__ uint32_t s_local_base[RADIX];
+  __shared__ uint32_t s_global_base[RADIX];
+  __shared__ uint32_t s_scan[kSortWaves];
+
+  const int64_t b = blockIdx.x;
+  const int64_t M = item_count(count, max_items);
+  if (b * kSortTile >= M) return;   // uniform over the block
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  // this block's offsets and the digit totals, in flight while the keys load
+  const uint32_t my_off = (tid < RADIX) ? offsets[(int64_t)tid * n_blocks + b] : 0u;
+  const uint32_t dtot = (tid < RADIX) ? totals[tid] : 0u;
+  for (int i = tid; i < kSortWaves * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
+  uint32_t k[kSortItems], val[kSortItems], dig[kSortItems], rank[kSortItems];
+  load_block_keys<DB>(keys_in, b, M, shift, k, dig);
+  {
+    const int64_t wbase = b * kSortTile + (int64_t)wave * (kSortTile / kSortWaves);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const int64_t i = wbase + (int64_t)r * kWave + lane;
+      val[r] = (i < M) ? vals_in[i] : 0u;
+    }
+  }
+  __syncthreads();
+  wave_rank<DB>(dig, rank, s_whist[wave]);
+  __syncthreads();
+  // per digit: exclusive offsets of the waves, block total
+  uint32_t total = 0;
+  if (tid < RADIX) {
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      const uint32_t c = s_whist[w][tid];
+      s_whist[w][tid] = total;
+      total += c;
+    }
+  }
+  uint32_t unused;
+  const uint32_t start = block_excl_scan256(dtot, s_scan, &unused);
+  const uint32_t local = block_excl_scan256(total, s_scan, &unused);
+  if (tid < RADIX) {
+    s_local_base[tid] = local;
+    s_global_base[tid] = start + my_off;
+  }
   __syncthreads();
   // reorder through LDS into block-sorted order
 #pragma unroll
@@ -277,13 +269,13 @@ radix_pass(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ va
     }
   }
   __syncthreads();
-  const int n_valid = (int)min((int64_t)kSortTile, M - tile * kSortTile);
-  for (int s = tid; s < n_valid; s += kSortBlock) {
-    const uint32_t kk = s_keys[s];
+  const int n_valid = (int)min((int64_t)kSortTile, M - b * kSortTile);
+  for (int i = tid; i < n_valid; i += kSortBlock) {
+    const uint32_t kk = s_keys[i];
     const uint32_t d = (kk >> shift) & (RADIX - 1);
-    const uint32_t g = s_global_base[d] + ((uint32_t)s - s_local_base[d]);
+    const uint32_t g = s_global_base[d] + ((uint32_t)i - s_local_base[d]);
     keys_out[g] = kk;
-    vals_out[g] = s_vals[s];
+    vals_out[g] = s_vals[i];
   }
 }
 
@@ -292,27 +284,23 @@ int radix_passes(int key_bits, int digit_bits) {
 }
 
 int radix_sort(const RadixBufs& b, int start, const uint32_t* count, int64_t max_items,
-               int key_bits, int db, void* ws, size_t ws_bytes, uint32_t* status,
-               hipStream_t s) {
+               int key_bits, int db, void* ws, size_t ws_bytes, hipStream_t s) {
   const int passes = radix_passes(key_bits, db);
   if (passes > kMaxPasses) return GS_ERR_UNSUPPORTED;
   if (passes == 0 || max_items <= 0) return GS_OK;
   if (ws_bytes < radix_workspace_bytes(max_items, passes)) return GS_ERR_ARG;
   RadixWs w = carve(ws, max_items);
-  radix_init<<<dim3((unsigned)std::min<int64_t>(w.n_blocks, 1024)), 256, 0, s>>>(
-      w, passes, count, max_items);
-  const int src0 = start & 1;
-  const unsigned hb = (unsigned)std::min<int64_t>(w.n_blocks, 2048);
-  radix_histogram<<<dim3(hb), 256, 0, s>>>(b.keys[src0], count, max_items, passes, db, w.hist);
-  radix_scan_hist<<<1, 256, 0, s>>>(w.hist, passes);
   const dim3 grid((unsigned)w.n_blocks);
   for (int p = 0; p < passes; ++p) {
     const int src = (start + p) & 1, dst = src ^ 1;
-    uint32_t* lb = w.lookback + (size_t)p * w.n_blocks * 256;
 #define GS_LAUNCH_PASS(D)                                                                        \
-  radix_pass<D><<<grid, kSortBlock, 0, s>>>(b.keys[src], b.vals[src], b.keys[dst], b.vals[dst],  \
-                                            count, max_items, p * db, w.hist + p * 256, lb,      \
-                                            w.ticket + p, status)
+  radix_count<D><<<grid, kSortBlock, 0, s>>>(b.keys[src], count, max_items, p * db, w.n_blocks,  \
+                                             w.counts);                                          \
+  radix_scan_counts<<<dim3(1u << D), kSortBlock, 0, s>>>(w.counts, count, max_items, w.n_blocks, \
+                                                         w.totals);                              \
+  radix_scatter<D><<<grid, kSortBlock, 0, s>>>(b.keys[src], b.vals[src], b.keys[dst],            \
+                                               b.vals[dst], count, max_items, p * db,            \
+                                               w.n_blocks, w.counts, w.totals)
     switch (db) {
       case 4: GS_LAUNCH_PASS(4); break;
       case 5: GS_LAUNCH_PASS(5); break;
@@ -473,7 +461,7 @@ static int sort_impl(const gs_instances* inst, int64_t n_tiles_total, const gs_c
   const InstanceBufs b = instance_bufs(inst, passes);
   const int64_t cap = inst->capacity;
   int rc = radix_sort(b.tiles, 0, inst->count, cap, bits, cfg->sort_digit_bits, workspace,
-                      workspace_bytes, inst->status, s);
+                      workspace_bytes, s);
   if (rc != GS_OK) return rc;
   sort_ranges<<<dim3((unsigned)((n_tiles_total + 255) / 256)), 256, 0, s>>>(
       b.sorted_tiles, inst->count, cap, n_tiles_total, tile_ranges);
