@@ -144,10 +144,22 @@ radix_count(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ coun
   if (b * kSortTile >= M) return;   // uniform over the block
   const int tid = threadIdx.x, wave = tid / kWave;
   for (int i = tid; i < kSortWaves * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
-  uint32_t k[kSortItems], dig[kSortItems], rank[kSortItems];
+  uint32_t k[kSortItems], dig[kSortItems];
   load_block_keys<DB>(keys, b, M, shift, k, dig);
   __syncthreads();
-  wave_rank<DB>(dig, rank, s_whist[wave]);
+  // counts need no ranks: LDS adds into the wave's own counters. Lanes of one add that
+  // share a digit serialise on its word, so the lanes holding lane 0's digit (the
+  // common digit of a skewed pass, such as the top bits of the depth keys) are counted
+  // with one ballot and one add, and only the others add one each.
+  const int lane = tid % kWave;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t d = dig[r];
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t same = __ballot(d == d0);
+    if (lane == 0 && d0 < (uint32_t)RADIX) atomicAdd(&s_whist[wave][d0], (uint32_t)__popcll(same));
+    if (d != d0 && d < (uint32_t)RADIX) atomicAdd(&s_whist[wave][d], 1u);
+  }
   __syncthreads();
   if (tid < RADIX) {
     uint32_t c = 0;
