@@ -111,10 +111,10 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
 // colour (FP32), so their registers are not live at the same time
 // ---------------------------------------------------------------------------
 
-// Three waves per SIMD (at most 168 VGPRs, 84 bytes per lane spilled) instead of the
-// two that 188 VGPRs allow: the kernel waits on memory most of its time, and the
-// third wave hides more of it than the spills cost (0.51 against 0.56 ms at 3M
-// Gaussians x 4 views; four waves, at 152 bytes of spills, take 0.80 ms).
+// Three waves per SIMD: the kernel waits on memory most of its time, so the third wave
+// pays (0.56 ms at two waves, 188 VGPRs; 0.51 ms at three with 84 bytes per lane
+// spilled; 0.48 ms now that the geometry loop fits 156 VGPRs without spills, at 3M
+// Gaussians x 4 views). Four waves spill 112 bytes per lane and take 0.93 ms.
 template <int DEG>
 __global__ void __launch_bounds__(kProjBlock) __attribute__((amdgpu_waves_per_eu(3)))
 project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -133,10 +133,22 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   float dmu_f[3] = {0.0f, 0.0f, 0.0f};
   {
   double ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, s[3] = {0, 0, 0};
-  double dop = 0.0, opac = 0.0;
+  float dop = 0.0f;
+  double opac = 0.0;
   const bool iso = rules.isotropic != 0;
+  // the unit quaternion and 1 / |q|: formed before the view loop for R, and again after
+  // it from the same inputs (not held through the loop, whose FP64 chain sets the
+  // kernel's register peak)
+  auto unit_quat = [&](double* qh) {
+    const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
+    const double iq = rsqrt_d(fma(q0, q0, fma(q1, q1, fma(q2, q2, q3 * q3))));
+    qh[0] = q0 * iq;
+    qh[1] = q1 * iq;
+    qh[2] = q2 * iq;
+    qh[3] = q3 * iq;
+    return iq;
+  };
   if (any) {
-    double qh[4] = {1.0, 0.0, 0.0, 0.0}, iq = 1.0;
     double M[9];
     {
     double R[9];
@@ -146,12 +158,8 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
       s[0] = s[1] = s[2] = exp((((double)log_scales[g] + (double)log_scales[n + g]) +
                                (double)log_scales[2 * n + g]) / 3.0);
     } else {
-      const double q0 = quats[g], q1 = quats[n + g], q2 = quats[2 * n + g], q3 = quats[3 * n + g];
-      iq = rsqrt_d(fma(q0, q0, fma(q1, q1, fma(q2, q2, q3 * q3))));
-      qh[0] = q0 * iq;
-      qh[1] = q1 * iq;
-      qh[2] = q2 * iq;
-      qh[3] = q3 * iq;
+      double qh[4];
+      unit_quat(qh);
       quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
       s[0] = exp((double)log_scales[g]);
       s[1] = exp((double)log_scales[n + g]);
@@ -160,7 +168,6 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * s[c];
     }
-    opac = rcp_d(1.0 + exp(fmin(-(double)logits[g], 700.0)));   // exp capped: rcp_d(inf) is NaN
     // the view loop accumulates in FP32 (the gradients' own precision); every
     // per-view term is formed in FP64
     float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -191,12 +198,19 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
       const double fx = cam.fx, fy = cam.fy, tx = p.tx, ty = p.ty;
       const double iz = p.iz, iz2 = iz * iz, iz3 = iz2 * iz;
       const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
+      // dJ_rc = dA_r . (W M)_c = W_c . (M dA_r): through M, so that W M need not stay
+      // live from the covariance to here
+      double m0[3], m1[3];
+      for (int i = 0; i < 3; ++i) {
+        m0[i] = M[i * 3 + 0] * dA0[0] + M[i * 3 + 1] * dA0[1] + M[i * 3 + 2] * dA0[2];
+        m1[i] = M[i * 3 + 0] * dA1[0] + M[i * 3 + 1] * dA1[1] + M[i * 3 + 2] * dA1[2];
+      }
       double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
-      for (int k = 0; k < 3; ++k) {
-        dJ00 += dA0[k] * p.WM[0 * 3 + k];
-        dJ02 += dA0[k] * p.WM[2 * 3 + k];
-        dJ11 += dA1[k] * p.WM[1 * 3 + k];
-        dJ12 += dA1[k] * p.WM[2 * 3 + k];
+      for (int i = 0; i < 3; ++i) {
+        dJ00 += (double)cam.R[0 * 3 + i] * m0[i];
+        dJ02 += (double)cam.R[2 * 3 + i] * m0[i];
+        dJ11 += (double)cam.R[1 * 3 + i] * m1[i];
+        dJ12 += (double)cam.R[2 * 3 + i] * m1[i];
       }
       // A = U M with U = J W (rows U0 = J00 W0 + J02 W2, U1 = J11 W1 + J12 W2):
       // dM += U^T dA
@@ -215,13 +229,16 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
         dmu_f[k] += (float)((double)cam.R[0 * 3 + k] * dtx + (double)cam.R[1 * 3 + k] * dty +
                             (double)cam.R[2 * 3 + k] * dtz);
     }
+    opac = rcp_d(1.0 + exp(fmin(-(double)logits[g], 700.0)));   // exp capped: rcp_d(inf) is NaN
     // M = R diag(s): dR_ij = dM_ij s_j, ds_j = sum_i dM_ij R_ij (R recomputed here
     // rather than held through the view loop)
     double R[9];
+    double qh[4] = {1.0, 0.0, 0.0, 0.0}, iq = 1.0;
     if (iso) {
       R[0] = R[4] = R[8] = 1.0;
       R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.0;
     } else {
+      iq = unit_quat(qh);
       quat_to_rot(qh[0], qh[1], qh[2], qh[3], R);
     }
     double dR[9];
@@ -253,7 +270,7 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   d_log_scales[n + g] = (float)(ds[1] * s[1]);
   d_log_scales[2 * n + g] = (float)(ds[2] * s[2]);
   for (int c = 0; c < 4; ++c) d_quats[(int64_t)c * n + g] = (float)dq[c];
-  d_logits[g] = (float)(dop * opac * (1.0 - opac));
+  d_logits[g] = (float)((double)dop * opac * (1.0 - opac));
   }
   // SH colour: coefficient gradients and the view-direction term of the mean. The
   // barrier keeps the coefficient loads from being hoisted into the geometry loop.
