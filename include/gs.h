@@ -3,9 +3,10 @@
  *
  * The method is the differentiable tile rasterizer of Kerbl et al., "3D Gaussian
  * Splatting for Real-Time Radiance Field Rendering" (SIGGRAPH 2023), Sec. 6 and
- * App. C, Alg. 2: Rasterize(w, h, M, S, C, A, V) over means M, covariances S
- * (stored as scales and rotation quaternions, Sec. 4), SH colours C (Sec. 5),
- * opacities A and a view V; and its backward pass (Sec. 6 and App. A).
+ * App. C and the rasterization procedure of Alg. 2: an image of given size from the
+ * Gaussians' means, covariances (stored as scales and rotation quaternions, Sec. 4),
+ * SH colours (Sec. 5) and opacities, seen from one camera; and its backward pass
+ * (Sec. 6 and App. A).
  *
  * One forward pass is
  *     gs_project -> gs_bin -> gs_sort -> gs_render_fwd
