@@ -1,7 +1,8 @@
 """Benchmark: 1080p forward+backward views/s at 3M Gaussians, batched vs per-view.
 
 One step = the whole hot path over one batch of views: project -> bin -> sort ->
-blend forward -> L1 loss gradient -> blend backward -> projection backward, on
+blend forward -> blend backward with the L1 loss and its gradient formed inside it ->
+projection backward, on
 seeded synthetic inputs resident in HBM (default: 3M Gaussians of the clustered-scene
 generator, SH degree 3, four 1920x1080 orbit cameras; targets rendered once from a
 jittered copy of the scene). ``value`` is the batched rate: all views of a step in one
@@ -84,7 +85,7 @@ def main():
 
     import scenes
     from paper_2308_04079_amd import GaussianParams, Rasterizer
-    from paper_2308_04079_amd.raster import GraphStep, l1_loss_grad
+    from paper_2308_04079_amd.raster import GraphStep
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -129,8 +130,8 @@ def main():
     def step(rs, cam_list, tgt):
         state = rs.render(params, cam_list, check=False)
         loss = zero_loss[:len(cam_list)].clone()
-        dL = l1_loss_grad(state, tgt, loss)
-        grads, _ = rs.backward(params, state, dL)
+        # the L1 gradient is formed inside the backward blend (gs_render_bwd_l1)
+        grads, _ = rs.backward(params, state, l1=(tgt, loss))
         return state, grads, loss
 
     def timed(fn, steps, dist=None):
@@ -311,7 +312,7 @@ def time_stages(rast, params, cams, target, steps, zero_loss):
 
     from paper_2308_04079_amd import _lib
     lib = _lib.lib()
-    names = ["project", "bin", "sort", "render_fwd", "loss", "render_bwd", "project_bwd"]
+    names = ["project", "bin", "sort", "render_fwd", "render_bwd", "project_bwd"]
     acc = {k: 0.0 for k in names}
     for _ in range(steps):
         st = rast.render(params, cams, check=False)
@@ -325,8 +326,9 @@ def time_stages(rast, params, cams, target, steps, zero_loss):
                              device="cuda")
         sort_ws = torch.empty(max(1, lib.gs_sort_workspace_bytes(st.capacity, st.n_tiles, cfg)),
                               dtype=torch.uint8, device="cuda")
-        dL = torch.empty_like(st.image)
         loss = zero_loss[:V].clone()
+        l1_ws = torch.empty(max(1, lib.gs_render_l1_workspace_bytes(st.cams_c, V, cfg)),
+                            dtype=torch.uint8, device="cuda")
         grad2d = torch.zeros(V * n * _lib.GRAD2D_FLOATS, dtype=torch.float32, device="cuda")
         grads = {k: torch.empty_like(getattr(params, k))
                  for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
@@ -344,12 +346,11 @@ def time_stages(rast, params, cams, target, steps, zero_loss):
             ("render_fwd", lambda: lib.gs_render_fwd(
                 ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), _lib.ptr(st.order),
                 st.cams_c, V, cfg, _lib.ptr(st.image), _lib.ptr(st.T_final), _lib.ptr(st.last_idx), n, stream)),
-            ("loss", lambda: lib.gs_loss_l1(_lib.ptr(st.image), _lib.ptr(target), st.cams_c, V,
-                                            _lib.ptr(dL), _lib.ptr(loss), stream)),
-            ("render_bwd", lambda: lib.gs_render_bwd(
+            ("render_bwd", lambda: lib.gs_render_bwd_l1(
                 ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(st.ranges), _lib.ptr(st.order),
-                st.cams_c, V, cfg, _lib.ptr(st.T_final), _lib.ptr(st.last_idx), _lib.ptr(dL), _lib.ptr(grad2d), n,
-                stream)),
+                st.cams_c, V, cfg, _lib.ptr(st.T_final), _lib.ptr(st.last_idx), _lib.ptr(st.image),
+                _lib.ptr(target), _lib.ptr(grad2d), _lib.ptr(loss), _lib.ptr(l1_ws), l1_ws.numel(),
+                n, stream)),
             ("project_bwd", lambda: lib.gs_project_bwd(ctypes.byref(pr), st.cams_c, V, cfg,
                                                        ctypes.byref(proj), _lib.ptr(grad2d),
                                                        ctypes.byref(gp), stream)),

@@ -267,6 +267,27 @@ int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
                   const gs_config* cfg, const float* T_final, const int32_t* last_idx,
                   const float* dL_dimage, float* grad2d, int64_t n, gs_stream_t stream);
 
+/* gs_render_bwd with the L1 photometric term of Sec. 5.1 taken inside it, for steps
+ * whose loss is L1 alone: instead of a stored dL/dimage, each pixel's upstream gradient
+ * is sign(image - target) / (3 H W) (sign(0) = 0), from the forward pass's image and the
+ * target (device, the image layout), exactly what gs_loss_l1 writes; grad2d receives
+ * what gs_render_bwd would add for that dL/dimage. If loss (device, V floats) is not
+ * NULL, each view's mean |image - target| over 3 H W is ADDED to loss[v], summed in a
+ * fixed order (the same bits on every run; equal to gs_loss_l1's up to that order);
+ * workspace: device scratch of gs_render_l1_workspace_bytes(cams, n_views, cfg) bytes
+ * (one float per 8x8 pixel block), owned by the caller and overwritten, unused (may be
+ * NULL) when loss is NULL; the query returns 0 for invalid cameras or config.
+ * image, target, T_final, last_idx or grad2d NULL, or a loss with a missing or short
+ * workspace: GS_ERR_ARG. */
+size_t gs_render_l1_workspace_bytes(const gs_camera* cams, int32_t n_views,
+                                    const gs_config* cfg);
+int gs_render_bwd_l1(const gs_projected* proj, const gs_instances* inst,
+                     const uint32_t* tile_ranges, const uint32_t* tile_order,
+                     const gs_camera* cams, int32_t n_views, const gs_config* cfg,
+                     const float* T_final, const int32_t* last_idx, const float* image,
+                     const float* target, float* grad2d, float* loss, void* workspace,
+                     size_t workspace_bytes, int64_t n, gs_stream_t stream);
+
 /* Projection backward (App. A chain rule, the quaternion normalisation, the
  * activations, SH and its view direction): gradients of the raw parameters,
  * summed over views, written (not accumulated) to *grads. */

@@ -100,6 +100,14 @@ EXPORTS = {
                                      ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int64, ctypes.c_void_p]),
+    "gs_render_l1_workspace_bytes": (ctypes.c_size_t, [P(GsCamera), ctypes.c_int32,
+                                                      P(GsConfig)]),
+    "gs_render_bwd_l1": (ctypes.c_int, [P(GsProjected), P(GsInstances), ctypes.c_void_p,
+                                        ctypes.c_void_p, P(GsCamera), ctypes.c_int32,
+                                        P(GsConfig), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_int64, ctypes.c_void_p]),
     "gs_project_bwd": (ctypes.c_int, [P(GsParams), P(GsCamera), ctypes.c_int32, P(GsConfig),
                                       P(GsProjected), ctypes.c_void_p, P(GsParamsGrad),
                                       ctypes.c_void_p]),

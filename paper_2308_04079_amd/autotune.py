@@ -16,7 +16,7 @@ import os
 
 import torch
 
-from .raster import Rasterizer, l1_loss_grad
+from .raster import Rasterizer
 
 TILE_SIZES = (8, 16, 32)
 LDS_BATCHES = (32, 64, 128)
@@ -37,15 +37,14 @@ def cache_key(params, cams) -> str:
 
 
 def time_step(rast: Rasterizer, params, cams, target, steps: int) -> float:
-    """Milliseconds of one forward + L1 gradient + backward, averaged over ``steps``."""
+    """Milliseconds of one forward + backward with the L1 loss, averaged over ``steps``."""
     state = rast.render(params, cams)                     # sizes the capacity
     rast.capacity = int(state.read_status()[1] * 1.15) + 4096
     loss = torch.zeros(len(cams), device=params.means.device)
 
     def one():
         st = rast.render(params, cams, check=False)
-        dL = l1_loss_grad(st, target, loss)
-        rast.backward(params, st, dL)
+        rast.backward(params, st, l1=(target, loss))
     one()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

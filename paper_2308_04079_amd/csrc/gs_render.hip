@@ -572,17 +572,35 @@ __device__ __forceinline__ int wave_max_int(int x) {
   return max(x, __shfl_xor(x, 32, kWave));
 }
 
-template <int TS, int BATCH, bool LIMIT>
+// The L1 term of the loss taken inside the backward (L1 = true): each pixel's upstream
+// gradient dL/dimage = sign(image - target) / (3 H W) (sign(0) = 0) is formed from the
+// forward's image and the target, instead of being read from a stored dL/dimage, and
+// the wave's share of the loss, mean |image - target| over 3 H W, goes to one slot per
+// wave (tile * waves per tile + wave), summed per view by loss_parts_kernel.
+struct L1In {
+  const float* image;    // flat image layout
+  const float* target;   // flat image layout
+  float* part;           // [tiles * waves per tile] per-wave loss shares; NULL: no loss
+};
+
+template <int TS, int BATCH, bool LIMIT, bool L1>
 __global__ void __launch_bounds__((TS / 8) * (TS / 8) * kWave)
 render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
                   TileViews tv, Rules rules, const float* __restrict__ T_final,
                   const int32_t* __restrict__ last_idx, const float* __restrict__ dL_dimage,
-                  float* __restrict__ grad2d) {
+                  float* __restrict__ grad2d, L1In l1) {
   constexpr int WPT = (TS / 8) * (TS / 8);
   __shared__ BwdLds<BATCH> s_lds[WPT];
   WaveTile w;
-  if (!wave_tile<TS>(tv, tile_order, w)) return;
+  if (!wave_tile<TS>(tv, tile_order, w)) {
+    if constexpr (L1) {
+      // a block outside the image still owns its loss slot: a zero share
+      if (l1.part && (uint32_t)w.tile < (uint32_t)tv.tile_offset[tv.n_views] && __lane_id() == 0)
+        l1.part[(int64_t)w.tile * WPT + threadIdx.x / kWave] = 0.0f;
+    }
+    return;
+  }
   BwdLds<BATCH>& s = s_lds[threadIdx.x / kWave];
   const int lane = threadIdx.x % kWave;
   // the wave's 8x8 block: lane l owns pixel (l & 7, l >> 3) of it
@@ -593,6 +611,7 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const float amax = rules.alpha_max;
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  float loss_share = 0.0f;   // this pixel's share of the view's L1 loss (L1 only)
   int32_t last = -1;
   if (inside) {
     const int64_t P = tv.pix_offset[w.v];
@@ -600,10 +619,29 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
     const int64_t p = (int64_t)py * w.W + px;
     T = T_final[P + p];
     last = last_idx[P + p];
-    const float* dimg = dL_dimage + 3 * P;
-    g0 = dimg[p];
-    g1 = dimg[HW + p];
-    g2 = dimg[2 * HW + p];
+    if constexpr (L1) {
+      const float inv = 1.0f / (3.0f * (float)HW);
+      const float* img = l1.image + 3 * P;
+      const float* tgt = l1.target + 3 * P;
+      const float d0 = img[p] - tgt[p], d1 = img[HW + p] - tgt[HW + p],
+                  d2 = img[2 * HW + p] - tgt[2 * HW + p];
+      g0 = d0 > 0.0f ? inv : (d0 < 0.0f ? -inv : 0.0f);
+      g1 = d1 > 0.0f ? inv : (d1 < 0.0f ? -inv : 0.0f);
+      g2 = d2 > 0.0f ? inv : (d2 < 0.0f ? -inv : 0.0f);
+      loss_share = fabsf(d0) * inv + fabsf(d1) * inv + fabsf(d2) * inv;
+    } else {
+      const float* dimg = dL_dimage + 3 * P;
+      g0 = dimg[p];
+      g1 = dimg[HW + p];
+      g2 = dimg[2 * HW + p];
+    }
+  }
+  if constexpr (L1) {
+    // before the early exit below: pixels that blended nothing still count in the loss
+    if (l1.part) {
+      loss_share = wave_sum_to_lane63(loss_share);
+      if (lane == kWave - 1) l1.part[(int64_t)w.tile * WPT + threadIdx.x / kWave] = loss_share;
+    }
   }
   // only g . B is ever needed, where B is the colour accumulated behind the current
   // Gaussian (initially T_final bg): dC/dalpha_i . g = T_i (g . c_i) - (g . B_i) / (1 - alpha_i)
@@ -696,6 +734,29 @@ render_bwd_kernel(const float* __restrict__ record, const uint32_t* __restrict__
       }
     }
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Sum of one view's per-wave L1 shares (blockIdx.x = view), in a fixed order, so that
+// the loss is the same on every run, added to loss[v]. Every wave of the view's tiles
+// wrote its slot (zero for blocks outside the image).
+constexpr int kPartThreads = 1024;
+
+__global__ void __launch_bounds__(kPartThreads)
+loss_parts_kernel(const float* __restrict__ part, TileViews tv, float* __restrict__ loss) {
+  __shared__ float s_sum[kPartThreads / kWave];
+  const int v = blockIdx.x;
+  const int64_t wpt = (int64_t)(tv.tile / 8) * (tv.tile / 8);
+  const int64_t b = (int64_t)tv.tile_offset[v] * wpt, e = (int64_t)tv.tile_offset[v + 1] * wpt;
+  float acc = 0.0f;
+  for (int64_t i = b + threadIdx.x; i < e; i += kPartThreads) acc += part[i];
+  acc = wave_sum_to_lane63(acc);
+  if (__lane_id() == kWave - 1) s_sum[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int k = 0; k < kPartThreads / kWave; ++k) t += s_sum[k];
+    atomicAdd(loss + v, t);
   }
 }
 
@@ -796,27 +857,22 @@ extern "C" int gs_loss_l1(const float* image, const float* target, const gs_came
   return launch_status();
 }
 
-extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
+template <bool L1>
+static int render_bwd_launch(const gs_projected* proj, const gs_instances* inst,
                              const uint32_t* tile_ranges, const uint32_t* tile_order,
-                             const gs_camera* cams, int32_t n_views,
-                             const gs_config* cfg, const float* T_final, const int32_t* last_idx,
-                             const float* dL_dimage, float* grad2d, int64_t n,
-                             gs_stream_t stream) {
-  TileViews tv;
-  int rc = render_common(proj, inst, tile_ranges, cams, n_views, cfg, n, &tv);
-  if (rc != GS_OK) return rc;
-  if (!T_final || !last_idx || !dL_dimage || !grad2d) return GS_ERR_ARG;
+                             const TileViews& tv, const gs_config* cfg, const float* T_final,
+                             const int32_t* last_idx, const float* dL_dimage, float* grad2d,
+                             L1In l1, hipStream_t s) {
   const Rules rules = make_rules(cfg);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const dim3 grid((unsigned)tv.tile_offset[n_views]);
+  const dim3 grid((unsigned)tv.tile_offset[tv.n_views]);
 #define GS_BWD(TS, B)                                                                          \
-  render_bwd_kernel<TS, B, false><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(               \
+  render_bwd_kernel<TS, B, false, L1><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(           \
       proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
-      dL_dimage, grad2d)
+      dL_dimage, grad2d, l1)
 #define GS_BWD_LIMITED(TS)                                                                     \
-  render_bwd_kernel<TS, 64, true><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(               \
+  render_bwd_kernel<TS, 64, true, L1><<<grid, (TS / 8) * (TS / 8) * kWave, 0, s>>>(           \
       proj->record, inst->vals, tile_ranges, tile_order, tv, rules, T_final, last_idx,         \
-      dL_dimage, grad2d)
+      dL_dimage, grad2d, l1)
   if (cfg->grad_limit > 0) {
     // the ablation path stages 64 entries per round whatever lds_batch says
     switch (cfg->tile_size) {
@@ -842,5 +898,53 @@ extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
       break;
   }
 #undef GS_BWD
+  return launch_status();
+}
+
+extern "C" int gs_render_bwd(const gs_projected* proj, const gs_instances* inst,
+                             const uint32_t* tile_ranges, const uint32_t* tile_order,
+                             const gs_camera* cams, int32_t n_views,
+                             const gs_config* cfg, const float* T_final, const int32_t* last_idx,
+                             const float* dL_dimage, float* grad2d, int64_t n,
+                             gs_stream_t stream) {
+  TileViews tv;
+  int rc = render_common(proj, inst, tile_ranges, cams, n_views, cfg, n, &tv);
+  if (rc != GS_OK) return rc;
+  if (!T_final || !last_idx || !dL_dimage || !grad2d) return GS_ERR_ARG;
+  return render_bwd_launch<false>(proj, inst, tile_ranges, tile_order, tv, cfg, T_final, last_idx,
+                                  dL_dimage, grad2d, L1In{nullptr, nullptr, nullptr},
+                                  reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t gs_render_l1_workspace_bytes(const gs_camera* cams, int32_t n_views,
+                                               const gs_config* cfg) {
+  if (!cfg || check_config(cfg) != GS_OK) return 0;
+  TileViews tv;
+  if (fill_tile_views(cams, n_views, cfg->tile_size, &tv) != GS_OK) return 0;
+  const size_t wpt = (size_t)(cfg->tile_size / 8) * (size_t)(cfg->tile_size / 8);
+  return (size_t)tv.tile_offset[n_views] * wpt * sizeof(float);
+}
+
+extern "C" int gs_render_bwd_l1(const gs_projected* proj, const gs_instances* inst,
+                                const uint32_t* tile_ranges, const uint32_t* tile_order,
+                                const gs_camera* cams, int32_t n_views, const gs_config* cfg,
+                                const float* T_final, const int32_t* last_idx, const float* image,
+                                const float* target, float* grad2d, float* loss, void* workspace,
+                                size_t workspace_bytes, int64_t n, gs_stream_t stream) {
+  TileViews tv;
+  int rc = render_common(proj, inst, tile_ranges, cams, n_views, cfg, n, &tv);
+  if (rc != GS_OK) return rc;
+  if (!T_final || !last_idx || !image || !target || !grad2d) return GS_ERR_ARG;
+  float* part = nullptr;
+  if (loss) {
+    const size_t need = gs_render_l1_workspace_bytes(cams, n_views, cfg);
+    if (need == 0 || !workspace || workspace_bytes < need) return GS_ERR_ARG;
+    part = static_cast<float*>(workspace);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  rc = render_bwd_launch<true>(proj, inst, tile_ranges, tile_order, tv, cfg, T_final, last_idx,
+                               nullptr, grad2d, L1In{image, target, part}, s);
+  if (rc != GS_OK || !loss) return rc;
+  loss_parts_kernel<<<(unsigned)n_views, kPartThreads, 0, s>>>(part, tv, loss);
   return launch_status();
 }

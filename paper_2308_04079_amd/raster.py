@@ -212,8 +212,12 @@ class Rasterizer:
         return state
 
     # -- backward ----------------------------------------------------------------
-    def backward(self, params: GaussianParams, state: RenderState, dL_dimage: torch.Tensor):
-        """Gradients of the raw parameters (dict of tensors shaped like ``params``)."""
+    def backward(self, params: GaussianParams, state: RenderState,
+                 dL_dimage: torch.Tensor | None = None, l1=None):
+        """Gradients of the raw parameters (dict of tensors shaped like ``params``), from
+        an upstream dL/dimage, or with ``l1=(target, loss)`` for the L1 loss alone taken
+        inside the backward blend (gs_render_bwd_l1): the per-view losses are added to
+        ``loss`` (a [V] tensor, or None), as l1_loss_grad does."""
         lib = _lib.lib()
         dev = params.means.device
         stream = torch.cuda.current_stream(dev).cuda_stream
@@ -221,17 +225,32 @@ class Rasterizer:
         V, n = state.n_views, state.n
         if state.T_final.numel() == 0:
             raise ValueError("the state was rendered with for_backward=False")
-        if dL_dimage.numel() != state.image.numel() or dL_dimage.dtype != torch.float32:
-            raise ValueError("dL_dimage must match the flat float32 image layout")
-        dL_dimage = dL_dimage.contiguous()
+        if (dL_dimage is None) == (l1 is None):
+            raise ValueError("give either dL_dimage or l1=(target, loss)")
         grad2d = torch.zeros(max(1, V * n * _lib.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
         proj = state.projected()
         inst = state.instances()
-        _lib.check("gs_render_bwd", lib.gs_render_bwd(
-            ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(state.ranges), _lib.ptr(state.order),
-            state.cams_c, V, cfg,
-            _lib.ptr(state.T_final), _lib.ptr(state.last_idx), _lib.ptr(dL_dimage),
-            _lib.ptr(grad2d), n, stream))
+        if l1 is None:
+            if dL_dimage.numel() != state.image.numel() or dL_dimage.dtype != torch.float32:
+                raise ValueError("dL_dimage must match the flat float32 image layout")
+            dL_dimage = dL_dimage.contiguous()
+            _lib.check("gs_render_bwd", lib.gs_render_bwd(
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(state.ranges), _lib.ptr(state.order),
+                state.cams_c, V, cfg,
+                _lib.ptr(state.T_final), _lib.ptr(state.last_idx), _lib.ptr(dL_dimage),
+                _lib.ptr(grad2d), n, stream))
+        else:
+            target, loss = l1
+            if target.numel() != state.image.numel() or target.dtype != torch.float32:
+                raise ValueError("the L1 target must match the flat float32 image layout")
+            target = target.contiguous()
+            ws = torch.empty(max(1, lib.gs_render_l1_workspace_bytes(state.cams_c, V, cfg)),
+                             dtype=torch.uint8, device=dev)
+            _lib.check("gs_render_bwd_l1", lib.gs_render_bwd_l1(
+                ctypes.byref(proj), ctypes.byref(inst), _lib.ptr(state.ranges), _lib.ptr(state.order),
+                state.cams_c, V, cfg, _lib.ptr(state.T_final), _lib.ptr(state.last_idx),
+                _lib.ptr(state.image), _lib.ptr(target), _lib.ptr(grad2d), _lib.ptr(loss),
+                _lib.ptr(ws), ws.numel(), n, stream))
         grads = {k: torch.empty_like(getattr(params, k))
                  for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
         k_active = (self.cfg.sh_degree + 1) ** 2
@@ -298,7 +317,7 @@ def rasterize(rasterizer: Rasterizer, cams, means, log_scales, quats, opacity_lo
 
 
 class GraphStep:
-    """One step (forward, L1 loss gradient, backward) captured in a HIP graph.
+    """One step (forward, backward with the L1 loss taken inside it) captured in a HIP graph.
 
     Every call of the captured sequence only enqueues kernels and allocates nothing
     outside torch's graph pool, so a replay re-runs the whole hot path with one
@@ -329,8 +348,7 @@ class GraphStep:
     def _body(self):
         state = self.rast.render(self.params, self.cams, check=False)
         loss = torch.zeros(len(self.cams), dtype=torch.float32, device=state.image.device)
-        dL = l1_loss_grad(state, self.target, loss)
-        grads, _ = self.rast.backward(self.params, state, dL)
+        grads, _ = self.rast.backward(self.params, state, l1=(self.target, loss))
         return state, grads, loss
 
     def replay(self):

@@ -155,6 +155,31 @@ def test_loss_argument_checks(L):
     assert lib.gs_loss_photometric(None, 1, cc, 1, 0.2, 1, None, ws, 16, None) == L.ERR_ARG
 
 
+def test_fused_l1_backward_argument_checks(L):
+    """gs_render_bwd_l1: one workspace float per 8x8 block of every tile; missing inputs
+    or (with a loss) a missing or short workspace are refused before any launch."""
+    import scenes
+    lib = L.lib()
+    cc = L.make_cameras([scenes.pinhole_camera(40, 30), scenes.pinhole_camera(17, 9)])
+    for ts, tiles in ((8, 5 * 4 + 3 * 2), (16, 3 * 2 + 2 * 1), (32, 2 * 1 + 1 * 1)):
+        cfg = L.default_config(tile_size=ts)
+        assert lib.gs_render_l1_workspace_bytes(cc, 2, ctypes.byref(cfg)) == tiles * (ts // 8) ** 2 * 4
+    assert lib.gs_render_l1_workspace_bytes(cc, 2, ctypes.byref(L.default_config(tile_size=12))) == 0
+    assert lib.gs_render_l1_workspace_bytes(cc, 0, ctypes.byref(L.default_config())) == 0
+    cfg = L.default_config()
+    need = lib.gs_render_l1_workspace_bytes(cc, 2, ctypes.byref(cfg))
+    proj = L.GsProjected(16, 16, 16)
+    inst = L.GsInstances(16, 16, 16, 16, 64, 16, 16)
+    ws = ctypes.create_string_buffer(need)
+    head = (ctypes.byref(proj), ctypes.byref(inst), 16, None, cc, 2, ctypes.byref(cfg), 16, 16)
+    # the pointers are never dereferenced: every call below fails its host checks
+    assert lib.gs_render_bwd_l1(*head, None, 16, 16, 16, ws, need, 10, None) == L.ERR_ARG
+    assert lib.gs_render_bwd_l1(*head, 16, None, 16, 16, ws, need, 10, None) == L.ERR_ARG
+    assert lib.gs_render_bwd_l1(*head, 16, 16, None, 16, ws, need, 10, None) == L.ERR_ARG
+    assert lib.gs_render_bwd_l1(*head, 16, 16, 16, 16, None, need, 10, None) == L.ERR_ARG
+    assert lib.gs_render_bwd_l1(*head, 16, 16, 16, 16, ws, need - 4, 10, None) == L.ERR_ARG
+
+
 def test_a_missing_library_fails_loudly():
     """No fallback: without the built library every entry raises."""
     import subprocess
