@@ -748,8 +748,16 @@ loss_parts_kernel(const float* __restrict__ part, TileViews tv, float* __restric
   const int v = blockIdx.x;
   const int64_t wpt = (int64_t)(tv.tile / 8) * (tv.tile / 8);
   const int64_t b = (int64_t)tv.tile_offset[v] * wpt, e = (int64_t)tv.tile_offset[v + 1] * wpt;
-  float acc = 0.0f;
-  for (int64_t i = b + threadIdx.x; i < e; i += kPartThreads) acc += part[i];
+  // eight independent loads in flight per pass, added in a fixed order
+  float a[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t i = b + threadIdx.x; i < e; i += 8 * kPartThreads) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t k = i + (int64_t)j * kPartThreads;
+      a[j] += (k < e) ? part[k] : 0.0f;
+    }
+  }
+  float acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   acc = wave_sum_to_lane63(acc);
   if (__lane_id() == kWave - 1) s_sum[threadIdx.x / kWave] = acc;
   __syncthreads();

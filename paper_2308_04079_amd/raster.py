@@ -179,8 +179,8 @@ class Rasterizer:
             vals = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
             keys_alt = torch.empty_like(keys)
             vals_alt = torch.empty_like(vals)
-            count = torch.zeros(1, dtype=torch.int32, device=dev)
-            status = torch.zeros(1, dtype=torch.int32, device=dev)
+            words = torch.zeros(2, dtype=torch.int32, device=dev)   # one fill for both
+            count, status = words[0:1], words[1:2]
             state = RenderState(n, cams, cams_c, V, int(n_tiles), list(toff), pix, depth_key,
                                 tiles_touched, record, keys, vals, keys_alt, vals_alt, count,
                                 status, cap, ranges, order, image, T_final, last_idx)
