@@ -22,7 +22,7 @@ namespace gs {
 constexpr int kBinBlock = 256;
 constexpr int kBinItems = 16;                       // per thread
 constexpr int kBinTile = kBinBlock * kBinItems;     // 4096 per block
-constexpr int kExpandOut = 2048;                    // instances per expansion block
+constexpr int kExpandOut = 1024;                    // instances per expansion block
 // misc words: [0] visible pairs, [1] the same clamped to the capacity, [4] the
 // instances of the (clamped) depth-sorted pairs. The exact instance count over all
 // pairs (64-bit, exact even when the capacity is short) is the sum of the per-block
