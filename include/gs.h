@@ -216,7 +216,7 @@ int gs_sort(const gs_instances* inst, int64_t n_tiles_total, const gs_config* cf
  * device array of GS_SORT_SCRATCH_BYTES, one per GPU, held until the process ends. The
  * call allocates and frees nothing. Limit: gs_sort_workspace_bytes(inst->capacity,
  * n_tiles_total, cfg) must not exceed GS_SORT_SCRATCH_BYTES (else GS_ERR_SCRATCH and
- * nothing is enqueued); 16 MiB covers about 67M instances (1 KiB per 4096).
+ * nothing is enqueued); 16 MiB covers about 50M instances (1 KiB per 3072).
  * The array belongs to the device current at the call (the stream must be on it); the
  * first call on a device looks up its address there (hipGetSymbolAddress: make that
  * first call outside graph capture). No part of the array needs to start at zero

@@ -8,7 +8,7 @@
 // 12 bytes over tile + depth bits.
 //
 // Each radix digit pass is reduce-then-scan, in three launches: a counting pass in
-// which every 256-thread block counts the digits of its 4096 keys (wave ballots find
+// which every 256-thread block counts the digits of its 3072 keys (wave ballots find
 // the lanes sharing a digit), a scan with one workgroup per digit over the blocks'
 // counts, and a scatter pass in which every block ranks its keys again, reorders them
 // through LDS and writes each digit's run contiguously at its scanned offset. The keys
@@ -23,8 +23,8 @@
 namespace gs {
 
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortBlock * kSortItems;   // 4096 keys per block
+constexpr int kSortItems = 12;
+constexpr int kSortTile = kSortBlock * kSortItems;   // 3072 keys per block
 constexpr int kSortWaves = kSortBlock / kWave;
 constexpr int kMaxPasses = 8;
 constexpr int kMaxRadix = 256;
@@ -61,7 +61,7 @@ __device__ __forceinline__ int64_t item_count(const uint32_t* count, int64_t max
   return min((int64_t)count[0], max_items);
 }
 
-// The block's keys: wave w owns the contiguous run [b*4096 + w*1024, +1024), round r
+// The block's keys: wave w owns the contiguous run [b*3072 + w*768, +768), round r
 // lane l its item r*64 + l. Digits of missing items are RADIX (no digit).
 template <int DB>
 __device__ __forceinline__ void load_block_keys(const uint32_t* __restrict__ keys, int64_t b,

@@ -103,9 +103,9 @@ def test_host_argument_checks_return_before_any_launch(L):
     assert lib.gs_sort_noalloc(ctypes.byref(fake), 8160, ctypes.byref(cfg), 16, None, None) == L.ERR_UNSUPPORTED
     assert lib.gs_sort_noalloc(ctypes.byref(fake), 8160, ctypes.byref(bad), 16, None, None) == L.ERR_ARG
     assert lib.gs_status_string(L.ERR_SCRATCH) == b"needs more than the library's static scratch"
-    # one set of per-block digit counts shared by the passes (256 words per 4096 keys)
+    # one set of per-block digit counts shared by the passes (256 words per 3072 keys)
     # and the digit totals, then the tile-order table (33 buckets per 1024 tiles)
-    blocks = (1 << 20) // 4096
+    blocks = -(-(1 << 20) // 3072)
     counts = (256 * blocks + 256) * 4
     assert lib.gs_sort_workspace_bytes(1 << 20, 8160, ctypes.byref(cfg)) == \
         ((counts + 255) // 256) * 256 + (8160 + 1023) // 1024 * 33 * 4
