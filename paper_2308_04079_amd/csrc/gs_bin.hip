@@ -20,8 +20,8 @@
 namespace gs {
 
 constexpr int kBinBlock = 256;
-constexpr int kBinItems = 16;                       // per thread
-constexpr int kBinTile = kBinBlock * kBinItems;     // 4096 per block
+constexpr int kBinItems = 8;                       // per thread
+constexpr int kBinTile = kBinBlock * kBinItems;     // 2048 per block
 constexpr int kExpandOut = 1024;                    // instances per expansion block
 // misc words: [0] visible pairs, [1] the same clamped to the capacity, [4] the
 // instances of the (clamped) depth-sorted pairs. The exact instance count over all
@@ -205,8 +205,8 @@ bin_scan_sums(uint32_t* __restrict__ sums, int64_t n_blocks, int64_t capacity,
   }
 }
 
-// The visible pairs of each 4096-block in index order, as (depth key, index) for
-// the sort. Sixteen rounds of 256 consecutive items; within a round a wave ballot
+// The visible pairs of each 2048-block in index order, as (depth key, index) for
+// the sort. Eight rounds of 256 consecutive items; within a round a wave ballot
 // and the per-wave totals give every visible item its position, so reads and
 // writes stay contiguous.
 __global__ void __launch_bounds__(kBinBlock)
@@ -255,8 +255,8 @@ bin_compact(const int32_t* __restrict__ touched, const uint32_t* __restrict__ de
   }
 }
 
-// LDS word of item i of a 4096-item block, padded by one word per 32 items so that
-// lanes reading 16 consecutive items each fall in different banks
+// LDS word of item i of a 2048-item block, padded by one word per 32 items so that
+// lanes reading kBinItems consecutive items each fall in different banks
 __device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
 
 // Start offset of every depth-sorted pair's instances: the block-local scan of the
@@ -269,7 +269,7 @@ bin_pair_offsets(const uint32_t* __restrict__ pair_wh,
                  const uint32_t* __restrict__ block_offsets, const uint32_t* __restrict__ n_out_dev,
                  int64_t capacity, uint32_t* __restrict__ offs, uint32_t* __restrict__ heads) {
   // the block's counts pass through LDS (one padded word per item) so that the global
-  // reads and writes are coalesced while each thread scans 16 consecutive items
+  // reads and writes are coalesced while each thread scans kBinItems consecutive items
   __shared__ uint32_t s_t[kBinTile + kBinTile / 32];
   __shared__ uint32_t s4[kBinBlock / kWave];
   const int64_t n_sorted = min((int64_t)n_sorted_dev[0], max_items);
@@ -371,7 +371,7 @@ struct BinWs {
   uint32_t* exp_sums;
   uint32_t* offs;            // instance offset of every pair in depth order
   uint32_t* pair_wh;         // tile rectangle width | height << 16 of every pair in depth order
-  unsigned long long* tile_parts;   // instance count of each 4096-pair block (index order)
+  unsigned long long* tile_parts;   // instance count of each 2048-pair block (index order)
   void* radix;
   size_t radix_bytes;
   int64_t nb;
