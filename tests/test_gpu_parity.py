@@ -284,11 +284,14 @@ def test_degenerate_gaussians_do_not_poison_the_image():
     sc.log_scales[:, 20:30] = -30.0           # vanishing scale: culled (empty box or det)
     sc.opacity_logits[30:35] = -800.0         # sigmoid far below any alpha_min: opacity 0
     sc.opacity_logits[35:40] = 800.0          # sigmoid 1: every alpha at the clamp
+    sc.sh[2, 1, 40:45] = np.inf               # a non-finite colour coefficient: culled
+    sc.sh[0, 0, 45:48] = np.nan
     cams = [scenes.pinhole_camera(64, 64)]
     _, _, state = gpu_render(sc, cams)
     img = gpu_images(state)[0][0]
     assert np.isfinite(img).all()
     assert np.all(to_np(state.tiles_touched)[:20] == 0)
+    assert np.all(to_np(state.tiles_touched)[40:48] == 0)
     g = decode_records(state, 0)
     assert np.all(g["opacity"][30:35][g["valid"][30:35]] == 0.0)
     assert np.all(g["opacity"][35:40][g["valid"][35:40]] == 1.0)
