@@ -71,7 +71,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU; runs over several GPUs are not part of it (use --gpus 1)"}))
         sys.exit(2)
     if args.mode == "train":
         return train(args)
