@@ -290,7 +290,9 @@ int gs_render_bwd_l1(const gs_projected* proj, const gs_instances* inst,
 
 /* Projection backward (App. A chain rule, the quaternion normalisation, the
  * activations, SH and its view direction): gradients of the raw parameters,
- * summed over views, written (not accumulated) to *grads. */
+ * summed over views, written (not accumulated) to *grads. grad2d (device) holds
+ * n_views * n rows of GS_GRAD2D_FLOATS as gs_render_bwd leaves them; every row may
+ * be read, and the values of rows whose pair has tiles_touched <= 0 are ignored. */
 int gs_project_bwd(const gs_params* params, const gs_camera* cams, int32_t n_views,
                    const gs_config* cfg, const gs_projected* proj, const float* grad2d,
                    const gs_params_grad* grads, gs_stream_t stream);

@@ -111,10 +111,44 @@ project_kernel(const float* __restrict__ means, const float* __restrict__ log_sc
 // colour (FP32), so their registers are not live at the same time
 // ---------------------------------------------------------------------------
 
+// One view's inputs of the geometry backward: the tile count and the first six
+// gradient components (2D mean, whitening, opacity).
+struct GeomRow {
+  int32_t touched;
+  float gr[6];
+};
+
+__device__ __forceinline__ GeomRow load_geom_row(const int32_t* __restrict__ tiles_touched,
+                                                 const float* __restrict__ grad2d, int64_t idx) {
+  GeomRow r;
+  r.touched = tiles_touched[idx];
+  const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.gr[k] = gr[k];
+  return r;
+}
+
+// The colour backward's: the tile count and the three colour components.
+struct ColourRow {
+  int32_t touched;
+  float gr[3];
+};
+
+__device__ __forceinline__ ColourRow load_colour_row(const int32_t* __restrict__ tiles_touched,
+                                                     const float* __restrict__ grad2d, int64_t idx) {
+  ColourRow r;
+  r.touched = tiles_touched[idx];
+  const float* gr = grad2d + idx * GS_GRAD2D_FLOATS + 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.gr[k] = gr[k];
+  return r;
+}
+
 // Three waves per SIMD: the kernel waits on memory most of its time, so the third wave
 // pays (0.56 ms at two waves, 188 VGPRs; 0.51 ms at three with 84 bytes per lane
-// spilled; 0.48 ms now that the geometry loop fits 156 VGPRs without spills, at 3M
-// Gaussians x 4 views). Four waves spill 112 bytes per lane and take 0.93 ms.
+// spilled; 0.48 ms once the geometry loop fit 156 VGPRs without spills; 0.41 ms with
+// each view's inputs loaded one view ahead, 166 VGPRs, at 3M Gaussians x 4 views).
+// Four waves spill 112 bytes per lane and take 0.93 ms.
 template <int DEG>
 __global__ void __launch_bounds__(kProjBlock) __attribute__((amdgpu_waves_per_eu(3)))
 project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -171,15 +205,20 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
     // the view loop accumulates in FP32 (the gradients' own precision); every
     // per-view term is formed in FP64
     float dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // the next view's tile count and gradient row are loaded one view ahead, so that
+    // their memory latency overlaps the current view's FP64 chain (every row exists:
+    // grad2d holds V * n rows, zero where a pair is not visible)
+    GeomRow nxt = load_geom_row(tiles_touched, grad2d, g);
     for (int v = 0; v < views.n_views; ++v) {
-      const int64_t idx = (int64_t)v * n + g;
-      if (tiles_touched[idx] <= 0) continue;
+      const GeomRow cur = nxt;
+      if (v + 1 < views.n_views) nxt = load_geom_row(tiles_touched, grad2d, (int64_t)(v + 1) * n + g);
+      if (cur.touched <= 0) continue;
       const Cam& cam = views.cam[v];
       ProjGeom p;
       project_covariance(cam, rules, x, y, z, M, p);
-      const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
-      const double du = gr[0], dv = gr[1], dw00 = gr[2], dw10 = gr[3], dw11 = gr[4];
-      dop += gr[5];
+      const double du = cur.gr[0], dv = cur.gr[1], dw00 = cur.gr[2], dw10 = cur.gr[3],
+                   dw11 = cur.gr[4];
+      dop += cur.gr[5];
       // whitening W = L^-1: w00 = a^-1/2, w10 = -b / sqrt(a det), w11 = sqrt(a / det)
       const double a = p.a, b = p.b, c = p.c;
       const double sa = sqrt_d(a), isa = rcp_d(sa), isd = rsqrt_d(p.det);
@@ -281,20 +320,21 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   if (any) {
     float shc[K][3];
     load_sh<K>(sh, n, g, shc);
+    ColourRow nxt = load_colour_row(tiles_touched, grad2d, g);   // one view ahead, as above
     for (int v = 0; v < views.n_views; ++v) {
-      const int64_t idx = (int64_t)v * n + g;
-      if (tiles_touched[idx] <= 0) continue;
+      const ColourRow cur = nxt;
+      if (v + 1 < views.n_views) nxt = load_colour_row(tiles_touched, grad2d, (int64_t)(v + 1) * n + g);
+      if (cur.touched <= 0) continue;
       const Cam& cam = views.cam[v];
       float d[3];
       const float dist = view_dir(cam, x, y, z, d);
       float Y[K];
       sh_basis<DEG>(d[0], d[1], d[2], Y);
-      const float* gr = grad2d + idx * GS_GRAD2D_FLOATS;
       float dcol[3];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         // the forward clamped the colour at 0: no gradient through a clamped channel
-        dcol[ch] = (sh_colour_raw<K>(shc, Y, ch) >= 0.0f) ? gr[6 + ch] : 0.0f;
+        dcol[ch] = (sh_colour_raw<K>(shc, Y, ch) >= 0.0f) ? cur.gr[ch] : 0.0f;
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) dshc[kk][ch] = fmaf(Y[kk], dcol[ch], dshc[kk][ch]);
       }
