@@ -147,7 +147,7 @@ __device__ __forceinline__ ColourRow load_colour_row(const int32_t* __restrict__
 // Three waves per SIMD: the kernel waits on memory most of its time, so the third wave
 // pays (0.56 ms at two waves, 188 VGPRs; 0.51 ms at three with 84 bytes per lane
 // spilled; 0.48 ms once the geometry loop fit 156 VGPRs without spills; 0.41 ms with
-// each view's inputs loaded one view ahead, 166 VGPRs, at 3M Gaussians x 4 views).
+// each view's inputs loaded one view ahead, 167 VGPRs, at 3M Gaussians x 4 views).
 // Four waves spill 112 bytes per lane and take 0.93 ms.
 template <int DEG>
 __global__ void __launch_bounds__(kProjBlock) __attribute__((amdgpu_waves_per_eu(3)))
@@ -161,8 +161,11 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   if (g >= n) return;
-  bool any = false;
-  for (int v = 0; v < views.n_views; ++v) any = any || tiles_touched[(int64_t)v * n + g] > 0;
+  // the first view's row is loaded before everything else (see the geometry loop);
+  // bitwise ORs, so that every view's count is loaded at once, without branches
+  const GeomRow first = load_geom_row(tiles_touched, grad2d, g);
+  bool any = first.touched > 0;
+  for (int v = 1; v < views.n_views; ++v) any = any | (tiles_touched[(int64_t)v * n + g] > 0);
   const double x = means[g], y = means[n + g], z = means[2 * n + g];
   float dmu_f[3] = {0.0f, 0.0f, 0.0f};
   {
@@ -208,7 +211,7 @@ project_bwd_kernel(const float* __restrict__ means, const float* __restrict__ lo
     // the next view's tile count and gradient row are loaded one view ahead, so that
     // their memory latency overlaps the current view's FP64 chain (every row exists:
     // grad2d holds V * n rows, zero where a pair is not visible)
-    GeomRow nxt = load_geom_row(tiles_touched, grad2d, g);
+    GeomRow nxt = first;
     for (int v = 0; v < views.n_views; ++v) {
       const GeomRow cur = nxt;
       if (v + 1 < views.n_views) nxt = load_geom_row(tiles_touched, grad2d, (int64_t)(v + 1) * n + g);
