@@ -61,6 +61,23 @@ __device__ __forceinline__ int64_t item_count(const uint32_t* count, int64_t max
   return min((int64_t)count[0], max_items);
 }
 
+// Logical block (the run of keys [b * kSortTile, +kSortTile)) of workgroup blockIdx.x.
+// Workgroups go to the eight XCDs in turn, so workgroup p runs on XCD p % 8; block b
+// is given to workgroup (b % chunk) * 8 + b / chunk, with chunk = ceil(nb / 8) for the nb
+// blocks that hold keys: each XCD takes a contiguous range of blocks, and the
+// neighbouring blocks whose digit runs share cache lines in the scatter write them
+// through the same L2, which merges the partial lines before they go to memory (bin
+// 0.415 -> 0.38 ms, sort 0.185 -> 0.16 ms at 3M Gaussians x 4 views, against
+// workgroup b taking block b). The grid is a multiple of 8 of at least nb workgroups;
+// a workgroup without a block returns -1.
+__device__ __forceinline__ int64_t logical_block(int64_t M) {
+  const int64_t nb = (M + kSortTile - 1) / kSortTile;
+  const int64_t chunk = (nb + 7) / 8;
+  const int64_t x = blockIdx.x % 8, i = blockIdx.x / 8;
+  const int64_t b = x * chunk + i;
+  return (i < chunk && b < nb) ? b : -1;
+}
+
 // The block's keys: wave w owns the contiguous run [b*3072 + w*768, +768), round r
 // lane l its item r*64 + l. Digits of missing items are RADIX (no digit).
 template <int DB>
@@ -131,17 +148,17 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s, 
   return before + incl - x;
 }
 
-// Counting pass: block b's digit counts to counts[d][b]. Blocks past the keys write
-// nothing (the scan and the scatter stop at the last block holding keys).
+// Counting pass: block b's digit counts to counts[d][b]. Workgroups without a block
+// write nothing (the scan and the scatter stop at the last block holding keys).
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
 radix_count(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count,
             int64_t max_items, int shift, int64_t n_blocks, uint32_t* __restrict__ counts) {
   constexpr int RADIX = 1 << DB;
   __shared__ uint32_t s_whist[kSortWaves][RADIX];
-  const int64_t b = blockIdx.x;
   const int64_t M = item_count(count, max_items);
-  if (b * kSortTile >= M) return;   // uniform over the block
+  const int64_t b = logical_block(M);
+  if (b < 0) return;   // uniform over the block
   const int tid = threadIdx.x, wave = tid / kWave;
   for (int i = tid; i < kSortWaves * RADIX; i += kSortBlock) (&s_whist[0][0])[i] = 0;
   uint32_t k[kSortItems], dig[kSortItems];
@@ -232,9 +249,9 @@ radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__
   __shared__ uint32_t s_global_base[RADIX];
   __shared__ uint32_t s_scan[kSortWaves];
 
-  const int64_t b = blockIdx.x;
   const int64_t M = item_count(count, max_items);
-  if (b * kSortTile >= M) return;   // uniform over the block
+  const int64_t b = logical_block(M);
+  if (b < 0) return;   // uniform over the block
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   // this block's offsets and the digit totals, in flight while the keys load
   const uint32_t my_off = (tid < RADIX) ? offsets[(int64_t)tid * n_blocks + b] : 0u;
@@ -302,7 +319,7 @@ int radix_sort(const RadixBufs& b, int start, const uint32_t* count, int64_t max
   if (passes == 0 || max_items <= 0) return GS_OK;
   if (ws_bytes < radix_workspace_bytes(max_items, passes)) return GS_ERR_ARG;
   RadixWs w = carve(ws, max_items);
-  const dim3 grid((unsigned)w.n_blocks);
+  const dim3 grid((unsigned)((w.n_blocks + 7) / 8 * 8));   // a multiple of 8: logical_block
   for (int p = 0; p < passes; ++p) {
     const int src = (start + p) & 1, dst = src ^ 1;
 #define GS_LAUNCH_PASS(D)                                                                        \
