@@ -516,7 +516,8 @@ def hbm_rates(ms, st, count, n, V, K, digit_bits):
     (key and value read and written), 8 B written per instance; sort: 16 B per
     instance per tile-id pass; project_bwd: parameters read and gradients written
     (2 x 4 (11 + 3K) B per Gaussian), tile counts, and per visible (view, Gaussian) its
-    record and its 36 B screen-space gradient.
+    36 B screen-space gradient (the kernel recomputes the projection: it reads no
+    records).
     """
     from paper_2308_04079_amd import _lib
     vis = int((st.tiles_touched[:V * n] > 0).sum().item())
@@ -526,7 +527,7 @@ def hbm_rates(ms, st, count, n, V, K, digit_bits):
     b = {"project": par * n + 8 * V * n + 48 * vis,
          "bin": 4 * V * n + (12 + 16 * depth_passes) * vis + 8 * count,
          "sort": 16 * count * tile_passes,
-         "project_bwd": 2 * par * n + 4 * V * n + (48 + 36) * vis}
+         "project_bwd": 2 * par * n + 4 * V * n + 36 * vis}
     out = {}
     for k, v in b.items():
         gbs = v / (ms[k] * 1e-3) / 1e9
