@@ -1,7 +1,8 @@
 """gs_sort on tile ids written straight into the instance buffers (where the binning's
 expansion writes them), for key distributions the rendered scenes reach only by chance:
 a single tile, two tiles, a dominant tile, descending ids, block-sized and ragged
-counts, odd and even numbers of digit passes, and a count above the capacity. The
+counts (including the edges of the per-XCD ranges of key blocks), odd and even numbers
+of digit passes, and a count above the capacity. The
 result must be the stable sort of the tile ids (values keep their input order within a
 tile), with the tile ranges and a longest-first tile order."""
 import ctypes
@@ -82,6 +83,11 @@ def _sort(tiles, n_tiles, capacity, count, digit_bits):
     ("random", 300, 4097, 8),                 # one key into a second block
     ("random", 300, 1, 8),
     ("random", 64, 0, 8),
+    # the XCD-ordered block mapping: 8 blocks of 3072 keys (one per XCD), one key more
+    # (9 blocks: ranges of 2 and 1), and a count whose last XCD range is partial
+    ("random", 32640, 8 * 3072, 8),
+    ("random", 32640, 8 * 3072 + 1, 8),
+    ("dominant", 32640, 1_000_003, 7),
 ])
 def test_stable_tile_sort(kind, n_tiles, m, digit_bits):
     rng = np.random.default_rng(1000 + m + n_tiles)
